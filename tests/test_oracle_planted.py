@@ -1,0 +1,77 @@
+"""Planted mistakes: each plausible slip in the oracle must make a pin fail.
+
+Every case patches the oracle (on the CPU only), runs one of the pins of
+test_oracle_pins.py and expects it to fail; the patch is undone afterwards.
+"""
+import numpy as np
+import pytest
+
+import tests.test_oracle_pins as P
+from oracle import gates as G
+from oracle import sim
+
+
+def _expect_failure(fn, *args):
+    with pytest.raises(AssertionError):
+        fn(*args)
+
+
+def test_transposed_ry_is_caught(monkeypatch):
+    monkeypatch.setattr(G, "RY", lambda t: G.RY.__wrapped__(t).T if hasattr(G.RY, "__wrapped__")
+                        else np.array([[np.cos(t / 2), np.sin(t / 2)], [-np.sin(t / 2), np.cos(t / 2)]],
+                                      dtype=complex))
+    _expect_failure(P.test_rotations_are_exponentials, 0.7)
+
+
+def test_missing_half_angle_in_rz_is_caught(monkeypatch):
+    monkeypatch.setattr(G, "RZ", lambda t: np.diag([np.exp(-1j * t), np.exp(1j * t)]))
+    monkeypatch.setitem(G.PARAM, "RZ", (G.RZ, G.dRZ))
+    _expect_failure(P.test_rz_layer_eigenphase, 3)
+
+
+def test_flipped_wire_order_is_caught(monkeypatch):
+    def counting_lsb_first(n):
+        j = np.arange(2 ** n)
+        return ((j[:, None] >> np.arange(n)[None, :]) & 1).astype(np.int64)
+    monkeypatch.setattr(sim, "counting_matrix", counting_lsb_first)
+    _expect_failure(P.test_k_rz_worked_example_sec241)
+    _expect_failure(P.test_expval_wire_order)
+
+
+def test_reversed_ring_order_is_caught(monkeypatch):
+    orig = sim.pattern_wires
+
+    def reversed_ring(n, ly):
+        w = orig(n, ly)
+        return w[::-1] if ly.pattern == "RING" else w
+    monkeypatch.setattr(sim, "pattern_wires", reversed_ring)
+    _expect_failure(P.test_ry_then_cnot_ring_closed_form, 4)
+
+
+def test_ring_without_wrap_pair_is_caught(monkeypatch):
+    orig = sim.pattern_wires
+
+    def open_ring(n, ly):
+        w = orig(n, ly)
+        return w[:-1] if ly.pattern == "RING" and n > 2 else w
+    monkeypatch.setattr(sim, "pattern_wires", open_ring)
+    _expect_failure(P.test_zz_ring_uses_k_rzz, 4)
+
+
+def test_adjoint_missing_factor_two_is_caught(monkeypatch):
+    orig = G.generator
+    monkeypatch.setattr(G, "generator", lambda gate, t: 0.5 * orig(gate, t))
+    _expect_failure(P.test_gradient_routes_agree, P.GRAD_CASES[0])
+
+
+def test_transposed_cnot_control_is_caught(monkeypatch):
+    swapped = np.array([[1, 0, 0, 0], [0, 0, 0, 1], [0, 0, 1, 0], [0, 1, 0, 0]], dtype=complex)
+    monkeypatch.setitem(G.FIXED, "CNOT", lambda: swapped)
+    _expect_failure(P.test_sigma_cnot_sec23)
+
+
+def test_wrong_ecr_row_is_caught(monkeypatch):
+    bad = G.ECR().copy()
+    bad[2, 1] = -bad[2, 1]
+    monkeypatch.setitem(G.FIXED, "ECR", lambda: bad)
+    _expect_failure(P.test_all_gates_unitary)
