@@ -1,0 +1,168 @@
+/*
+ * tqsim.h -- C ABI of libtqsim, a batched state-vector simulator of layered
+ * quantum-machine-learning circuits for AMD MI355X (gfx950).
+ *
+ * The operations follow the problem statement of arXiv 2506.04891 ("TQml
+ * Simulator"): an n-qubit state is a vector psi of 2^n complex amplitudes
+ * (Sec. 1); a circuit is an ordered list of layers of uniformly placed gates
+ * (Sec. 1, Fig. 6); each layer evolves the state as psi' = U psi with U the
+ * layer's 2^n x 2^n unitary (Sec. 2.2.1); the readout is the single-qubit
+ * observables <Z_i> (Figs. 6 and 11); training needs the derivatives of the
+ * readout with respect to the circuit's weights and its input features (Sec. 3).
+ *
+ * Conventions
+ *   - Amplitude index j = sum_k b_k 2^(n-1-k): wire 0 is the most significant
+ *     bit (the bit order of the binary counting matrix J, Sec. 2.4.1).
+ *   - State buffers are [batch, 2^n] row-major, interleaved (re, im):
+ *     TQS_C64 = 2 x float (8 bytes per amplitude), TQS_C128 = 2 x double.
+ *   - Weights, features, expectation values and gradients are always double.
+ *   - Gate matrices are those of the paper's Appendix A.  Rotation angles are
+ *     radians; GPI / GPI2 phases and the MS angle are in turns.  ECR is read as
+ *     (I(x)X - X(x)Y)/sqrt(2) (its printed rows 0-1; rows 2-3 as printed are not
+ *     unitary) and MS as MS(0, 0, theta) = exp(-i pi theta X(x)X).
+ *
+ * Ownership and execution
+ *   - The caller owns every device buffer and the stream.  Calls that take a
+ *     stream only enqueue work on it (asynchronous, stream-ordered); they do not
+ *     allocate device memory, do not synchronise and read no device data on the
+ *     host, so they may be captured into a HIP graph once the circuit has been
+ *     used outside capture (the first use uploads the circuit's plan).
+ *   - A circuit is immutable after creation and may be used concurrently on
+ *     different streams with distinct state and workspace buffers.
+ *
+ * Errors
+ *   Every call returns a tqs_status.  Argument, layer-list and size errors give
+ *   TQS_EINVAL before anything is enqueued; an undersized workspace gives
+ *   TQS_ENOMEM; a HIP runtime or launch failure gives TQS_EDEVICE.
+ *   tqs_last_error() returns a thread-local description of the last failure.
+ */
+#ifndef TQSIM_H
+#define TQSIM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  TQS_OK = 0,
+  TQS_EINVAL = 1,        /* invalid argument, layer list or size            */
+  TQS_ENOMEM = 2,        /* workspace smaller than tqs_workspace_size()     */
+  TQS_EDEVICE = 3,       /* HIP runtime / launch failure                    */
+  TQS_EUNSUPPORTED = 4   /* valid request that this build does not provide  */
+} tqs_status;
+
+typedef enum { TQS_C64 = 0, TQS_C128 = 1 } tqs_dtype;
+
+/* Gates of the paper's Table 1 / Appendix A (Rot is not provided). */
+typedef enum {
+  TQS_RX = 0, TQS_RY = 1, TQS_RZ = 2, TQS_H = 3, TQS_X = 4, TQS_Z = 5, TQS_S = 6,
+  TQS_SX = 7, TQS_GPI = 8, TQS_GPI2 = 9,                       /* 1-qubit */
+  TQS_CNOT = 10, TQS_CZ = 11, TQS_SWAP = 12, TQS_ZZ = 13, TQS_MS = 14,
+  TQS_ECR = 15                                                 /* 2-qubit */
+} tqs_gate;
+
+typedef enum {
+  TQS_ALL = 0,         /* the 1-qubit gate on every wire 0..n-1                    */
+  TQS_WIRE = 1,        /* one gate on `wire` (2-qubit: on (wire, wire2))           */
+  TQS_RING = 2,        /* (i, i+1 mod n), i = 0..n-1 in order; n=2: (0,1); n=1: none */
+  TQS_CHAIN = 3,       /* (i, i+1), i = 0..n-2 in order                            */
+  TQS_PAIRS_EVEN = 4,  /* (2i, 2i+1); n even                                       */
+  TQS_PAIRS_ODD = 5    /* (2i+1, 2i+2 mod n); n even                               */
+} tqs_pattern;
+
+typedef enum {
+  TQS_FIXED = 0,       /* every gate of the layer uses fixed_param                 */
+  TQS_WEIGHT = 1,      /* gate k of the layer uses weights[offset + k]             */
+  TQS_INPUT = 2        /* gate k uses features[b * n_features + offset + k]        */
+} tqs_source;
+
+typedef struct {
+  int32_t gate;        /* tqs_gate                                                 */
+  int32_t pattern;     /* tqs_pattern                                              */
+  int32_t source;      /* tqs_source (ignored for gates without a parameter)       */
+  int32_t wire;        /* TQS_WIRE: the wire (first wire of a 2-qubit gate)        */
+  int32_t wire2;       /* TQS_WIRE, 2-qubit gates: the second wire                 */
+  int32_t offset;      /* first weight index / feature column of the layer         */
+  double fixed_param;  /* parameter used when source == TQS_FIXED                  */
+} tqs_layer;
+
+typedef struct tqs_circuit tqs_circuit;
+typedef struct ihipStream_t *tqs_stream;   /* hipStream_t; NULL = default stream */
+
+/* Validate a layer list and compile its execution plan (host only; no device
+ * memory is touched until the first forward call).  n_qubits in [1, 30];
+ * parameters of a layer must fit in the weights / features implied by the
+ * largest offset + count.  *out receives a new circuit (free with
+ * tqs_circuit_destroy).  EINVAL for: n out of range, an unknown gate / pattern /
+ * source, a pattern invalid for the gate's arity, repeated or out-of-range
+ * wires, PAIRS patterns with odd n, negative offsets. */
+tqs_status tqs_circuit_create(int32_t n_qubits, const tqs_layer *layers, int32_t n_layers,
+                              tqs_dtype dtype, tqs_circuit **out);
+
+/* Free a circuit and its device tables.  Safe on NULL. */
+tqs_status tqs_circuit_destroy(tqs_circuit *c);
+
+/* Number of weights and feature columns the circuit reads, and the state size
+ * of one sample in bytes (2^n times 8 or 16).  Any pointer may be NULL. */
+tqs_status tqs_circuit_info(const tqs_circuit *c, int32_t *n_weights, int32_t *n_features,
+                            int64_t *state_bytes_per_sample);
+
+/* Device workspace (bytes) needed by tqs_forward / tqs_expval_z /
+ * tqs_adjoint_grad for `batch` samples; with_grad != 0 includes the adjoint
+ * buffers.  The same workspace may serve all three calls in sequence. */
+tqs_status tqs_workspace_size(const tqs_circuit *c, int32_t batch, int32_t with_grad,
+                              size_t *bytes);
+
+/* Forward pass: psi_b = U_L ... U_1 |0...0> for every sample.
+ *   weights_d   device, [n_weights] double (may be NULL if n_weights == 0)
+ *   features_d  device, [batch, n_features] double row-major (NULL if none)
+ *   state_d     device, [batch, 2^n] complex of the circuit's dtype; written
+ *   ws_d        device workspace of ws_bytes >= tqs_workspace_size(batch, 0)
+ * Enqueued on stream s. */
+tqs_status tqs_forward(tqs_circuit *c, int32_t batch, const double *weights_d,
+                       const double *features_d, void *state_d, void *ws_d, size_t ws_bytes,
+                       tqs_stream s);
+
+/* Readout: expz[b, i] = <psi_b| Z_i |psi_b> (Z_i = +1 on bit value 0 of wire i),
+ * accumulated in double; norm[b] = <psi_b|psi_b> when norm_d != NULL.
+ *   state_d [batch, 2^n] (read only); expz_d [batch, n] double; norm_d [batch]. */
+tqs_status tqs_expval_z(const tqs_circuit *c, int32_t batch, const void *state_d,
+                        double *expz_d, double *norm_d, void *ws_d, size_t ws_bytes,
+                        tqs_stream s);
+
+/* Adjoint gradient of L = sum_{b,i} g[b,i] <Z_i>_b (the adjoint method cited in
+ * Sec. 2.1): lambda = (sum_i g_i Z_i) psi, then layer by layer in reverse the
+ * derivative 2 Im <lambda|G|psi> of every parameter is accumulated (G the gate's
+ * output-side generator) and psi, lambda are uncomputed with the inverse layer;
+ * no intermediate state is stored.
+ *   state_d        in: the final states of tqs_forward (same weights/features);
+ *                  clobbered.
+ *   grad_expz_d    [batch, n] double, upstream dL/d<Z_i>.
+ *   grad_weights_d [n_weights] double, overwritten (may be NULL if n_weights == 0).
+ *   grad_features_d [batch, n_features] double, overwritten; NULL to skip.
+ *   ws_d           ws_bytes >= tqs_workspace_size(batch, 1). */
+tqs_status tqs_adjoint_grad(tqs_circuit *c, int32_t batch, const double *weights_d,
+                            const double *features_d, void *state_d, const double *grad_expz_d,
+                            double *grad_weights_d, double *grad_features_d, void *ws_d,
+                            size_t ws_bytes, tqs_stream s);
+
+/* Dispatcher override, before the first forward call.  Keys:
+ *   "mode"       0 = auto, 1 = per-layer passes (one technique per layer),
+ *                2 = fused passes, 3 = dense (full layer unitaries, n <= 8)
+ *   "tile_bits"  0 = auto, else K in [10, 12] for multi-pass plans
+ * EINVAL for an unknown key or value, or after the plan has been uploaded. */
+tqs_status tqs_set_option(tqs_circuit *c, const char *key, int64_t value);
+
+/* JSON description of the execution plan (passes, tiles, stages, kernels). */
+tqs_status tqs_plan_describe(const tqs_circuit *c, char *buf, size_t len);
+
+const char *tqs_status_string(tqs_status st);
+const char *tqs_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* TQSIM_H */

@@ -1,0 +1,1309 @@
+// gfx950 kernels of libtqsim.
+//
+//   k_prep       -- FP64 gate matrices, diagonal phase angles and gradient
+//                   coefficients from the weights / features (one thread per
+//                   item and sample), rounded once to the state dtype.
+//   k_pass       -- one HBM pass of the batched state: load a 2^K tile into LDS
+//                   (or generate the embedded product state), run the pass's
+//                   stages, store.  The backward instantiation uncomputes psi
+//                   and lambda with the inverse ops and accumulates gradient
+//                   partial sums before each inverse op.
+//   k_expval     -- <Z_i> partial sums (the paper's K_Rz^T |psi|^2, Sec. 2.4.1).
+//   k_adj_init   -- lambda = (sum_i g_i Z_i) psi.
+//   k_acc_reduce / k_grad_combine / k_expval_final -- deterministic FP64
+//                   reductions of the per-segment partial sums.
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "plan.h"
+
+namespace tqs {
+
+template <typename T>
+struct __align__(2 * sizeof(T)) cplx {
+  T x, y;
+};
+
+template <typename T>
+__device__ __forceinline__ cplx<T> cmk(T x, T y) {
+  cplx<T> r;
+  r.x = x;
+  r.y = y;
+  return r;
+}
+template <typename T>
+__device__ __forceinline__ cplx<T> cadd(cplx<T> a, cplx<T> b) {
+  return cmk(a.x + b.x, a.y + b.y);
+}
+template <typename T>
+__device__ __forceinline__ cplx<T> cmul(cplx<T> a, cplx<T> b) {
+  return cmk(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+// conj(a) * b
+template <typename T>
+__device__ __forceinline__ cplx<T> cjmul(cplx<T> a, cplx<T> b) {
+  return cmk(a.x * b.x + a.y * b.y, a.x * b.y - a.y * b.x);
+}
+template <typename T>
+__device__ __forceinline__ cplx<T> cconj(cplx<T> a) {
+  return cmk(a.x, -a.y);
+}
+// m * a + n * b
+template <typename T>
+__device__ __forceinline__ cplx<T> cfma2(cplx<T> m, cplx<T> a, cplx<T> n, cplx<T> b) {
+  cplx<T> r;
+  r.x = m.x * a.x - m.y * a.y + n.x * b.x - n.y * b.y;
+  r.y = m.x * a.y + m.y * a.x + n.x * b.y + n.y * b.x;
+  return r;
+}
+
+// LDS swizzle: XOR-fold the higher index groups into the lowest group so that
+// 16 (8-byte) or 8 (16-byte) lanes walking any four / three distinct bit
+// classes hit distinct banks.  GF(2)-linear, so swz(a ^ b) = swz(a) ^ swz(b).
+template <typename T>
+__device__ __forceinline__ int swz(int t);
+template <>
+__device__ __forceinline__ int swz<float>(int t) {
+  return t ^ ((t >> 4) & 15) ^ ((t >> 8) & 15);
+}
+template <>
+__device__ __forceinline__ int swz<double>(int t) {
+  return t ^ ((t >> 3) & 7) ^ ((t >> 6) & 7) ^ ((t >> 9) & 7);
+}
+
+// Plan tables are read by every lane at the same address; readfirstlane makes
+// the values wave-uniform (SGPRs) so that op dispatch stays scalar control flow.
+__device__ __forceinline__ int uni(int x) { return __builtin_amdgcn_readfirstlane(x); }
+__device__ __forceinline__ uint32_t uniu(uint32_t x) {
+  return (uint32_t)__builtin_amdgcn_readfirstlane((int)x);
+}
+
+struct UOp {
+  int kind, flags, r0, r1, mat, acc, aux;
+};
+__device__ __forceinline__ UOp load_op(const DevOp *p) {
+  UOp o;
+  o.kind = uni(p->kind);
+  o.flags = uni(p->flags);
+  o.r0 = uni(p->r0);
+  o.r1 = uni(p->r1);
+  o.mat = uni(p->mat);
+  o.acc = uni(p->acc);
+  o.aux = uni(p->aux);
+  return o;
+}
+struct UStage {
+  int rbits[RB];
+  int op_begin, op_end;
+};
+__device__ __forceinline__ UStage load_stage(const DevStage *p) {
+  UStage s;
+  s.rbits[0] = uni(p->rbits[0]);
+  s.rbits[1] = uni(p->rbits[1]);
+  s.rbits[2] = uni(p->rbits[2]);
+  s.rbits[3] = uni(p->rbits[3]);
+  s.op_begin = uni(p->op_begin);
+  s.op_end = uni(p->op_end);
+  return s;
+}
+
+// ---------------------------------------------------------------------------
+// FP64 gate library (the paper's Appendix A; ECR and MS as read in tqsim.h)
+// ---------------------------------------------------------------------------
+struct zd {
+  double x, y;
+};
+__device__ __forceinline__ zd zmk(double x, double y) {
+  zd r;
+  r.x = x;
+  r.y = y;
+  return r;
+}
+__device__ __forceinline__ zd zmul(zd a, zd b) { return zmk(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x); }
+__device__ __forceinline__ zd zadd(zd a, zd b) { return zmk(a.x + b.x, a.y + b.y); }
+__device__ __forceinline__ zd zconj(zd a) { return zmk(a.x, -a.y); }
+__device__ __forceinline__ zd zexpi(double t) {
+  double s, c;
+  sincos(t, &s, &c);
+  return zmk(c, s);
+}
+
+enum GateId {
+  G_RX = 0, G_RY = 1, G_RZ = 2, G_H = 3, G_X = 4, G_Z = 5, G_S = 6, G_SX = 7, G_GPI = 8, G_GPI2 = 9,
+  G_CNOT = 10, G_CZ = 11, G_SWAP = 12, G_ZZ = 13, G_MS = 14, G_ECR = 15,
+  G_GPI_DIAG = 100  // diagonal factor of GPI: diag(e^{2 pi i phi}, e^{-2 pi i phi})
+};
+
+constexpr double PI = 3.14159265358979323846;
+constexpr double RSQ2 = 0.70710678118654752440;
+
+// 2x2 matrix (row-major) and its derivative with respect to the parameter.
+__device__ void gate2(int g, double t, zd m[4], zd d[4]) {
+  for (int i = 0; i < 4; ++i) {
+    m[i] = zmk(0, 0);
+    d[i] = zmk(0, 0);
+  }
+  double s, c;
+  switch (g) {
+    case G_RX:
+      sincos(0.5 * t, &s, &c);
+      m[0] = zmk(c, 0); m[1] = zmk(0, -s); m[2] = zmk(0, -s); m[3] = zmk(c, 0);
+      d[0] = zmk(-0.5 * s, 0); d[1] = zmk(0, -0.5 * c); d[2] = zmk(0, -0.5 * c); d[3] = zmk(-0.5 * s, 0);
+      break;
+    case G_RY:
+      sincos(0.5 * t, &s, &c);
+      m[0] = zmk(c, 0); m[1] = zmk(-s, 0); m[2] = zmk(s, 0); m[3] = zmk(c, 0);
+      d[0] = zmk(-0.5 * s, 0); d[1] = zmk(-0.5 * c, 0); d[2] = zmk(0.5 * c, 0); d[3] = zmk(-0.5 * s, 0);
+      break;
+    case G_RZ: {
+      sincos(0.5 * t, &s, &c);
+      m[0] = zmk(c, -s); m[3] = zmk(c, s);
+      d[0] = zmk(-0.5 * s, -0.5 * c); d[3] = zmk(-0.5 * s, 0.5 * c);
+      break;
+    }
+    case G_H:
+      m[0] = zmk(RSQ2, 0); m[1] = zmk(RSQ2, 0); m[2] = zmk(RSQ2, 0); m[3] = zmk(-RSQ2, 0);
+      break;
+    case G_X:
+      m[1] = zmk(1, 0); m[2] = zmk(1, 0);
+      break;
+    case G_Z:
+      m[0] = zmk(1, 0); m[3] = zmk(-1, 0);
+      break;
+    case G_S:
+      m[0] = zmk(1, 0); m[3] = zmk(0, 1);
+      break;
+    case G_SX:
+      m[0] = zmk(0.5, 0.5); m[1] = zmk(0.5, -0.5); m[2] = zmk(0.5, -0.5); m[3] = zmk(0.5, 0.5);
+      break;
+    case G_GPI: {
+      zd e = zexpi(2.0 * PI * t);
+      m[1] = zconj(e); m[2] = e;
+      d[1] = zmul(zmk(0, -2.0 * PI), zconj(e)); d[2] = zmul(zmk(0, 2.0 * PI), e);
+      break;
+    }
+    case G_GPI2: {
+      zd e = zexpi(2.0 * PI * t);
+      m[0] = zmk(RSQ2, 0); m[3] = zmk(RSQ2, 0);
+      m[1] = zmul(zmk(0, -RSQ2), zconj(e)); m[2] = zmul(zmk(0, -RSQ2), e);
+      d[1] = zmul(zmk(-2.0 * PI * RSQ2, 0), zconj(e)); d[2] = zmul(zmk(2.0 * PI * RSQ2, 0), e);
+      break;
+    }
+    case G_GPI_DIAG: {
+      zd e = zexpi(2.0 * PI * t);
+      m[0] = e; m[3] = zconj(e);
+      d[0] = zmul(zmk(0, 2.0 * PI), e); d[3] = zmul(zmk(0, -2.0 * PI), zconj(e));
+      break;
+    }
+    default:
+      m[0] = zmk(1, 0); m[3] = zmk(1, 0);
+  }
+}
+
+// 4x4 matrix (row-major; first wire = more significant bit).
+__device__ void gate4(int g, double t, zd m[16]) {
+  for (int i = 0; i < 16; ++i) m[i] = zmk(0, 0);
+  switch (g) {
+    case G_CNOT:
+      m[0] = m[5] = m[11] = m[14] = zmk(1, 0);
+      break;
+    case G_CZ:
+      m[0] = m[5] = m[10] = zmk(1, 0); m[15] = zmk(-1, 0);
+      break;
+    case G_SWAP:
+      m[0] = m[6] = m[9] = m[15] = zmk(1, 0);
+      break;
+    case G_ZZ: {
+      zd a = zexpi(-0.5 * t), b = zexpi(0.5 * t);
+      m[0] = a; m[5] = b; m[10] = b; m[15] = a;
+      break;
+    }
+    case G_MS: {
+      double s, c;
+      sincos(PI * t, &s, &c);
+      m[0] = m[5] = m[10] = m[15] = zmk(c, 0);
+      m[3] = m[6] = m[9] = m[12] = zmk(0, -s);
+      break;
+    }
+    case G_ECR:
+      m[1] = zmk(RSQ2, 0); m[3] = zmk(0, RSQ2);
+      m[4] = zmk(RSQ2, 0); m[6] = zmk(0, -RSQ2);
+      m[9] = zmk(0, RSQ2); m[11] = zmk(RSQ2, 0);
+      m[12] = zmk(0, -RSQ2); m[14] = zmk(RSQ2, 0);
+      break;
+    default:
+      m[0] = m[5] = m[10] = m[15] = zmk(1, 0);
+  }
+}
+
+// Phase angles phi(v) of a diagonal gate, e^{i phi(v)}, v in bit order.
+__device__ int diag_angles(int g, double t, double a[4], double da[4]) {
+  for (int i = 0; i < 4; ++i) a[i] = da[i] = 0.0;
+  switch (g) {
+    case G_RZ: a[0] = -0.5 * t; a[1] = 0.5 * t; da[0] = -0.5; da[1] = 0.5; return 1;
+    case G_Z: a[1] = PI; return 1;
+    case G_S: a[1] = 0.5 * PI; return 1;
+    case G_GPI_DIAG: a[0] = 2.0 * PI * t; a[1] = -2.0 * PI * t; da[0] = 2.0 * PI; da[1] = -2.0 * PI; return 1;
+    case G_ZZ: a[0] = a[3] = -0.5 * t; a[1] = a[2] = 0.5 * t; da[0] = da[3] = -0.5; da[1] = da[2] = 0.5; return 2;
+    case G_CZ: a[3] = PI; return 2;
+  }
+  return 1;
+}
+
+__device__ __forceinline__ double factor_param(const Factor &f, const double *w, const double *x,
+                                               int nfeat, int b) {
+  if (f.src == 1) return w[f.pidx];
+  if (f.src == 2) return x[(size_t)b * nfeat + f.pidx];
+  return f.fixed;
+}
+
+__device__ __forceinline__ void mat2mul(const zd a[4], const zd b[4], zd r[4]) {
+  zd t[4];
+  t[0] = zadd(zmul(a[0], b[0]), zmul(a[1], b[2]));
+  t[1] = zadd(zmul(a[0], b[1]), zmul(a[1], b[3]));
+  t[2] = zadd(zmul(a[2], b[0]), zmul(a[3], b[2]));
+  t[3] = zadd(zmul(a[2], b[1]), zmul(a[3], b[3]));
+  for (int i = 0; i < 4; ++i) r[i] = t[i];
+}
+// a * b^dagger
+__device__ __forceinline__ void mat2mul_dag(const zd a[4], const zd b[4], zd r[4]) {
+  zd t[4];
+  t[0] = zadd(zmul(a[0], zconj(b[0])), zmul(a[1], zconj(b[1])));
+  t[1] = zadd(zmul(a[0], zconj(b[2])), zmul(a[1], zconj(b[3])));
+  t[2] = zadd(zmul(a[2], zconj(b[0])), zmul(a[3], zconj(b[1])));
+  t[3] = zadd(zmul(a[2], zconj(b[2])), zmul(a[3], zconj(b[3])));
+  for (int i = 0; i < 4; ++i) r[i] = t[i];
+}
+
+template <typename T>
+struct PrepArgs {
+  const PrepItem *items;
+  const Factor *factors;
+  int n_items;
+  const double *w;
+  const double *x;
+  int nfeat;
+  int batch;
+  cplx<T> *mats;
+  cplx<T> *mats_ps;
+  int mats_ps_stride;
+  double *dbl;       // angles and coefficients (shared)
+  double *dbl_ps;    // per-sample
+  int dbl_ps_stride;
+};
+
+template <typename T>
+__global__ void __launch_bounds__(64) k_prep(PrepArgs<T> a) {
+  const int item = blockIdx.y;
+  const int b = blockIdx.x * 64 + threadIdx.x;
+  if (item >= a.n_items) return;
+  const PrepItem it = a.items[item];
+  if (it.per_sample ? (b >= a.batch) : (b != 0)) return;
+  const int bs = it.per_sample ? b : 0;
+  switch (it.kind) {
+    case PREP_MAT1: {
+      zd m[4], d[4], f[4];
+      m[0] = zmk(1, 0); m[1] = zmk(0, 0); m[2] = zmk(0, 0); m[3] = zmk(1, 0);
+      for (int k = it.f_begin; k < it.f_end; ++k) {
+        const Factor fc = a.factors[k];
+        gate2(fc.gate, factor_param(fc, a.w, a.x, a.nfeat, bs), f, d);
+        mat2mul(f, m, m);
+      }
+      cplx<T> *o = it.per_sample ? a.mats_ps + (size_t)bs * a.mats_ps_stride + it.out : a.mats + it.out;
+      for (int i = 0; i < 4; ++i) o[i] = cmk<T>((T)m[i].x, (T)m[i].y);
+      break;
+    }
+    case PREP_MAT2: {
+      zd m[16];
+      const Factor fc = a.factors[it.f_begin];
+      gate4(fc.gate, factor_param(fc, a.w, a.x, a.nfeat, bs), m);
+      cplx<T> *o = it.per_sample ? a.mats_ps + (size_t)bs * a.mats_ps_stride + it.out : a.mats + it.out;
+      for (int i = 0; i < 16; ++i) o[i] = cmk<T>((T)m[i].x, (T)m[i].y);
+      break;
+    }
+    case PREP_ANG: {
+      double ang[4], da[4];
+      const Factor fc = a.factors[it.f_begin];
+      int nb = diag_angles(fc.gate, factor_param(fc, a.w, a.x, a.nfeat, bs), ang, da);
+      double *o = it.per_sample ? a.dbl_ps + (size_t)bs * a.dbl_ps_stride + it.out : a.dbl + it.out;
+      for (int i = 0; i < (1 << nb); ++i) o[i] = ang[i];
+      break;
+    }
+    case PREP_COEF1: {
+      // h = V G V^dag with G = i dF F^dag of factor k and V the later factors.
+      zd f[4], d[4], g[4], v[4], tmp[4];
+      const Factor fk = a.factors[it.k];
+      gate2(fk.gate, factor_param(fk, a.w, a.x, a.nfeat, bs), f, d);
+      mat2mul_dag(d, f, g);
+      for (int i = 0; i < 4; ++i) g[i] = zmul(zmk(0, 1), g[i]);
+      v[0] = zmk(1, 0); v[1] = zmk(0, 0); v[2] = zmk(0, 0); v[3] = zmk(1, 0);
+      for (int k = it.k + 1; k < it.f_end; ++k) {
+        const Factor fc = a.factors[k];
+        gate2(fc.gate, factor_param(fc, a.w, a.x, a.nfeat, bs), f, d);
+        mat2mul(f, v, v);
+      }
+      mat2mul(v, g, tmp);
+      mat2mul_dag(tmp, v, g);
+      double *o = it.per_sample ? a.dbl_ps + (size_t)bs * a.dbl_ps_stride + it.out : a.dbl + it.out;
+      o[0] = 2.0 * g[1].x;             // 2 hx
+      o[1] = -2.0 * g[1].y;            // 2 hy
+      o[2] = g[0].x - g[3].x;          // 2 hz
+      break;
+    }
+    case PREP_COEF2: {
+      // output-side generators: MS(theta) -> pi X(x)X, ZZ(theta) -> Z(x)Z / 2; the
+      // kernel sums Im<l|P(x)P|p>, the coefficient is twice the generator scale.
+      double *o = it.per_sample ? a.dbl_ps + (size_t)bs * a.dbl_ps_stride + it.out : a.dbl + it.out;
+      o[0] = a.factors[it.f_begin].gate == G_MS ? 2.0 * PI : 1.0;
+      break;
+    }
+    case PREP_COEFD: {
+      double ang[4], da[4];
+      const Factor fc = a.factors[it.f_begin];
+      int nb = diag_angles(fc.gate, factor_param(fc, a.w, a.x, a.nfeat, bs), ang, da);
+      // dL/dtheta = -2 sum_v dphi(v) W(v) with W(v) = class sum; only the
+      // parity sum over all term bits has a nonzero weight for these gates.
+      double c = 0.0;
+      for (int v = 0; v < (1 << nb); ++v) c += da[v] * ((__popc(v) & 1) ? -1.0 : 1.0);
+      c *= -2.0 / (double)(1 << nb);
+      double *o = it.per_sample ? a.dbl_ps + (size_t)bs * a.dbl_ps_stride + it.out : a.dbl + it.out;
+      o[0] = c;
+      break;
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// register-level gate application on 16 amplitudes held by one thread
+// ---------------------------------------------------------------------------
+template <typename T, int R, bool ADJ>
+__device__ __forceinline__ void u1_apply(cplx<T> (&v)[NREG], const cplx<T> m[4]) {
+  cplx<T> m00 = m[0], m01 = m[1], m10 = m[2], m11 = m[3];
+  if (ADJ) {
+    m00 = cconj(m[0]); m01 = cconj(m[2]); m10 = cconj(m[1]); m11 = cconj(m[3]);
+  }
+#pragma unroll
+  for (int j = 0; j < NREG; ++j) {
+    if (j & (1 << R)) continue;
+    const cplx<T> a = v[j], b = v[j | (1 << R)];
+    v[j] = cfma2(m00, a, m01, b);
+    v[j | (1 << R)] = cfma2(m10, a, m11, b);
+  }
+}
+
+template <typename T, int R, bool ADJ>
+__device__ __forceinline__ void u1_apply_real(cplx<T> (&v)[NREG], const cplx<T> m[4]) {
+  T m00 = m[0].x, m01 = m[1].x, m10 = m[2].x, m11 = m[3].x;
+  if (ADJ) {
+    m01 = m[2].x; m10 = m[1].x;
+  }
+#pragma unroll
+  for (int j = 0; j < NREG; ++j) {
+    if (j & (1 << R)) continue;
+    const cplx<T> a = v[j], b = v[j | (1 << R)];
+    v[j] = cmk(m00 * a.x + m01 * b.x, m00 * a.y + m01 * b.y);
+    v[j | (1 << R)] = cmk(m10 * a.x + m11 * b.x, m10 * a.y + m11 * b.y);
+  }
+}
+
+template <typename T, int R, bool ADJ>
+__device__ __forceinline__ void u1_apply_diag(cplx<T> (&v)[NREG], const cplx<T> m[4]) {
+  const cplx<T> d0 = ADJ ? cconj(m[0]) : m[0], d1 = ADJ ? cconj(m[3]) : m[3];
+#pragma unroll
+  for (int j = 0; j < NREG; ++j) v[j] = cmul(v[j], (j & (1 << R)) ? d1 : d0);
+}
+
+// Pauli sums Im<l|X|p>, Im<l|Y|p>, Im<l|Z|p> over the pairs of register bit R.
+template <typename T, int R>
+__device__ __forceinline__ void u1_grad(const cplx<T> (&p)[NREG], const cplx<T> (&l)[NREG], T &sx,
+                                        T &sy, T &sz) {
+#pragma unroll
+  for (int j = 0; j < NREG; ++j) {
+    if (j & (1 << R)) continue;
+    const cplx<T> pa = p[j], pb = p[j | (1 << R)], la = l[j], lb = l[j | (1 << R)];
+    const cplx<T> u = cjmul(la, pb), w = cjmul(lb, pa);
+    sx += u.y + w.y;
+    sy += w.x - u.x;
+    sz += (la.x * pa.y - la.y * pa.x) - (lb.x * pb.y - lb.y * pb.x);
+  }
+}
+
+template <typename T, int R0, int R1, bool ADJ>
+__device__ __forceinline__ void u2_apply(cplx<T> (&v)[NREG], const cplx<T> *__restrict__ mg) {
+  // entry (r, c) of the applied matrix: U[r][c], or conj(U[c][r]) for the adjoint
+#define TQS_M(r, c) (ADJ ? cconj(mg[(c) * 4 + (r)]) : mg[(r) * 4 + (c)])
+  const cplx<T> m00 = TQS_M(0, 0), m01 = TQS_M(0, 1), m02 = TQS_M(0, 2), m03 = TQS_M(0, 3);
+  const cplx<T> m10 = TQS_M(1, 0), m11 = TQS_M(1, 1), m12 = TQS_M(1, 2), m13 = TQS_M(1, 3);
+  const cplx<T> m20 = TQS_M(2, 0), m21 = TQS_M(2, 1), m22 = TQS_M(2, 2), m23 = TQS_M(2, 3);
+  const cplx<T> m30 = TQS_M(3, 0), m31 = TQS_M(3, 1), m32 = TQS_M(3, 2), m33 = TQS_M(3, 3);
+#undef TQS_M
+#pragma unroll
+  for (int j = 0; j < NREG; ++j) {
+    if (j & ((1 << R0) | (1 << R1))) continue;
+    const int i0 = j, i1 = j | (1 << R1), i2 = j | (1 << R0), i3 = j | (1 << R0) | (1 << R1);
+    const cplx<T> a0 = v[i0], a1 = v[i1], a2 = v[i2], a3 = v[i3];
+    v[i0] = cadd(cfma2(m00, a0, m01, a1), cfma2(m02, a2, m03, a3));
+    v[i1] = cadd(cfma2(m10, a0, m11, a1), cfma2(m12, a2, m13, a3));
+    v[i2] = cadd(cfma2(m20, a0, m21, a1), cfma2(m22, a2, m23, a3));
+    v[i3] = cadd(cfma2(m30, a0, m31, a1), cfma2(m32, a2, m33, a3));
+  }
+}
+
+template <typename T>
+__device__ __forceinline__ cplx<T> pauli_row(int code, int bit, cplx<T> a, cplx<T> b, T &sgn) {
+  // returns (P psi) component for bit value `bit`, given psi components a (0) and b (1)
+  switch (code) {
+    case 1: return bit ? a : b;                                   // X
+    case 2: return bit ? cmk(-a.y, a.x) : cmk(b.y, -b.x);         // Y: (-i b, i a)
+    default: return bit ? cmk(-b.x, -b.y) : a;                    // Z
+  }
+}
+
+// Im<l| P_a (x) P_b |p> over quads of register bits (R0 = more significant).
+template <typename T, int R0, int R1>
+__device__ __forceinline__ T u2_grad(const cplx<T> (&p)[NREG], const cplx<T> (&l)[NREG], int code) {
+  const int ca = code & 3, cb = (code >> 2) & 3;
+  T acc = 0;
+  T dummy;
+#pragma unroll
+  for (int j = 0; j < NREG; ++j) {
+    if (j & ((1 << R0) | (1 << R1))) continue;
+    const int i0 = j, i1 = j | (1 << R1), i2 = j | (1 << R0), i3 = j | (1 << R0) | (1 << R1);
+    // apply P_b on the low bit, then P_a on the high bit
+    const cplx<T> q0 = pauli_row(cb, 0, p[i0], p[i1], dummy), q1 = pauli_row(cb, 1, p[i0], p[i1], dummy);
+    const cplx<T> q2 = pauli_row(cb, 0, p[i2], p[i3], dummy), q3 = pauli_row(cb, 1, p[i2], p[i3], dummy);
+    const cplx<T> r0 = pauli_row(ca, 0, q0, q2, dummy), r2 = pauli_row(ca, 1, q0, q2, dummy);
+    const cplx<T> r1 = pauli_row(ca, 0, q1, q3, dummy), r3 = pauli_row(ca, 1, q1, q3, dummy);
+    acc += cjmul(l[i0], r0).y + cjmul(l[i1], r1).y + cjmul(l[i2], r2).y + cjmul(l[i3], r3).y;
+  }
+  return acc;
+}
+
+// ---------------------------------------------------------------------------
+// pass kernel
+// ---------------------------------------------------------------------------
+template <typename T>
+struct PassArgs {
+  const DevPass *pass;
+  const DevStage *stages;
+  const DevOp *ops;
+  const DevDiag *diags;
+  const DevTerm *terms;
+  const DevPerm *perms;
+  const cplx<T> *mats;
+  const cplx<T> *mats_ps;
+  int mats_ps_stride;
+  const double *dbl;
+  const double *dbl_ps;
+  int dbl_ps_stride;
+  const cplx<T> *src0;
+  cplx<T> *dst0;
+  const cplx<T> *src1;
+  cplx<T> *dst1;
+  T *partials;
+  long long acc_region;   // first partial of this pass
+  int units;              // partial units per sample of this pass
+  int batch;
+};
+
+template <typename T>
+__device__ __forceinline__ T seg_reduce(T v, int seg_log) {
+  for (int m = 1; m < (1 << seg_log); m <<= 1) v += __shfl_xor(v, m);
+  return v;
+}
+
+template <typename T, int K>
+struct Ctx {
+  static constexpr int NT = 1 << (K - RB);
+  int tid, lane;
+  int n, nv;
+  int multi;            // several samples per workgroup
+  int sample0;          // first sample of the workgroup
+  uint32_t base;        // state-index bits of the tile (single-sample mode)
+  int seg_log;          // log2 threads per reduction segment
+  int units_wg_base;    // unit offset of this workgroup within its sample (single mode)
+};
+
+// Sample of a thread in multi-sample mode: the sample bits are the top thread bits
+// in every stage (register bits are always state bits).
+template <typename T, int K>
+__device__ __forceinline__ int thread_sample(const Ctx<T, K> &c, int batch) {
+  const int s = c.multi ? c.sample0 + (c.tid >> (c.nv - RB)) : c.sample0;
+  return s < batch ? s : batch - 1;   // padding samples of a ragged last workgroup
+}
+
+template <typename T, int K>
+__device__ __forceinline__ void write_acc(const Ctx<T, K> &c, const PassArgs<T> &a, T v, int acc) {
+  v = seg_reduce(v, c.seg_log);
+  if ((c.tid & ((1 << c.seg_log) - 1)) == 0) {
+    const int seg = c.tid >> c.seg_log;
+    int s, u;
+    if (c.multi) {
+      const int spt_log = (c.nv - RB) - c.seg_log;   // segments per sample (log2)
+      s = c.sample0 + (seg >> spt_log);
+      u = seg & ((1 << spt_log) - 1);
+    } else {
+      s = c.sample0;
+      u = c.units_wg_base + seg;
+    }
+    if (s < a.batch) a.partials[a.acc_region + ((long long)acc * a.batch + s) * a.units + u] = v;
+  }
+}
+
+template <typename T>
+__device__ __forceinline__ const cplx<T> *op_mat(const PassArgs<T> &a, const UOp &op, int s) {
+  return (op.flags & F_PERSAMPLE) ? a.mats_ps + (size_t)s * a.mats_ps_stride + op.mat : a.mats + op.mat;
+}
+
+// dispatch helpers on compile-time register bits.  Each case carries a distinct
+// empty asm comment so that the optimiser cannot merge the case bodies into
+// one body indexed through pointers (which would demote the register tile to
+// scratch memory); the comment emits no instruction.
+#define TQS_CASE_MARK(id) asm volatile("; tqs case " #id ::)
+template <typename T, bool ADJ>
+__device__ __forceinline__ void u1_dispatch(cplx<T> (&v)[NREG], const cplx<T> m[4], int r, int flags) {
+  if (flags & F_DIAGONAL) {
+    switch (r) {
+      case 0: TQS_CASE_MARK(d0); u1_apply_diag<T, 0, ADJ>(v, m); TQS_CASE_MARK(ed0); break;
+      case 1: TQS_CASE_MARK(d1); u1_apply_diag<T, 1, ADJ>(v, m); TQS_CASE_MARK(ed1); break;
+      case 2: TQS_CASE_MARK(d2); u1_apply_diag<T, 2, ADJ>(v, m); TQS_CASE_MARK(ed2); break;
+      default: TQS_CASE_MARK(d3); u1_apply_diag<T, 3, ADJ>(v, m); TQS_CASE_MARK(ed3); break;
+    }
+  } else if (flags & F_REAL) {
+    switch (r) {
+      case 0: TQS_CASE_MARK(r0); u1_apply_real<T, 0, ADJ>(v, m); TQS_CASE_MARK(er0); break;
+      case 1: TQS_CASE_MARK(r1); u1_apply_real<T, 1, ADJ>(v, m); TQS_CASE_MARK(er1); break;
+      case 2: TQS_CASE_MARK(r2); u1_apply_real<T, 2, ADJ>(v, m); TQS_CASE_MARK(er2); break;
+      default: TQS_CASE_MARK(r3); u1_apply_real<T, 3, ADJ>(v, m); TQS_CASE_MARK(er3); break;
+    }
+  } else {
+    switch (r) {
+      case 0: TQS_CASE_MARK(c0); u1_apply<T, 0, ADJ>(v, m); TQS_CASE_MARK(ec0); break;
+      case 1: TQS_CASE_MARK(c1); u1_apply<T, 1, ADJ>(v, m); TQS_CASE_MARK(ec1); break;
+      case 2: TQS_CASE_MARK(c2); u1_apply<T, 2, ADJ>(v, m); TQS_CASE_MARK(ec2); break;
+      default: TQS_CASE_MARK(c3); u1_apply<T, 3, ADJ>(v, m); TQS_CASE_MARK(ec3); break;
+    }
+  }
+}
+
+template <typename T>
+__device__ __forceinline__ void u1_grad_dispatch(const cplx<T> (&p)[NREG], const cplx<T> (&l)[NREG],
+                                                 int r, T &sx, T &sy, T &sz) {
+  switch (r) {
+    case 0: TQS_CASE_MARK(g0); u1_grad<T, 0>(p, l, sx, sy, sz); TQS_CASE_MARK(eg0); break;
+    case 1: TQS_CASE_MARK(g1); u1_grad<T, 1>(p, l, sx, sy, sz); TQS_CASE_MARK(eg1); break;
+    case 2: TQS_CASE_MARK(g2); u1_grad<T, 2>(p, l, sx, sy, sz); TQS_CASE_MARK(eg2); break;
+    default: TQS_CASE_MARK(g3); u1_grad<T, 3>(p, l, sx, sy, sz); TQS_CASE_MARK(eg3); break;
+  }
+}
+
+#define TQS_U2_CASES(X) \
+  X(0, 1) X(0, 2) X(0, 3) X(1, 0) X(1, 2) X(1, 3) X(2, 0) X(2, 1) X(2, 3) X(3, 0) X(3, 1) X(3, 2)
+
+template <typename T, bool ADJ>
+__device__ __forceinline__ void u2_dispatch(cplx<T> (&v)[NREG], const cplx<T> *m, int r0, int r1) {
+  switch (r0 * 4 + r1) {
+#define X(a, b) \
+  case a * 4 + b: TQS_CASE_MARK(u##a##b); u2_apply<T, a, b, ADJ>(v, m); TQS_CASE_MARK(eu##a##b); break;
+    TQS_U2_CASES(X)
+#undef X
+  }
+}
+
+template <typename T>
+__device__ __forceinline__ T u2_grad_dispatch(const cplx<T> (&p)[NREG], const cplx<T> (&l)[NREG], int r0,
+                                              int r1, int code) {
+  switch (r0 * 4 + r1) {
+#define X(a, b) \
+  case a * 4 + b: { TQS_CASE_MARK(q##a##b); const T r_ = u2_grad<T, a, b>(p, l, code); TQS_CASE_MARK(eq##a##b); return r_; }
+    TQS_U2_CASES(X)
+#undef X
+  }
+  return T(0);
+}
+
+// 16-point Walsh-Hadamard transform in registers: w[m] <- sum_j w[j] (-1)^{popc(j & m)}
+template <typename T>
+__device__ __forceinline__ void wht16(T (&w)[NREG]) {
+#pragma unroll
+  for (int r = 0; r < RB; ++r)
+#pragma unroll
+    for (int j = 0; j < NREG; ++j) {
+      if (j & (1 << r)) continue;
+      const T a = w[j], b = w[j | (1 << r)];
+      w[j] = a + b;
+      w[j | (1 << r)] = a - b;
+    }
+}
+
+template <typename T>
+__device__ __forceinline__ T wht_pick(const T (&w)[NREG], int m) {
+  switch (m) {
+#define C(i) \
+  case i: TQS_CASE_MARK(w##i); return w[i];
+    C(0) C(1) C(2) C(3) C(4) C(5) C(6) C(7) C(8) C(9) C(10) C(11) C(12) C(13) C(14)
+#undef C
+    default: TQS_CASE_MARK(w15); return w[15];
+  }
+}
+
+// Build the split phase tables of every diagonal op of the pass in LDS.
+template <typename T, int K>
+__device__ __forceinline__ void build_diag_tables(const Ctx<T, K> &c, const PassArgs<T> &a, cplx<T> *tab) {
+  const DevPass *P = a.pass;
+  const int nd = uni(P->n_diag), db = uni(P->diag_begin);
+  for (int di = 0; di < nd; ++di) {
+    const DevDiag *dg = a.diags + db + di;
+    const int h = uni(dg->h), nx = uni(dg->n_extra), off = uni(dg->lds_off);
+    const int tbeg = uni(dg->term_begin), tend = uni(dg->term_end);
+    const int ex0 = nx > 0 ? uni(dg->extra[0]) : -1, ex1 = nx > 1 ? uni(dg->extra[1]) : -1;
+    const int nl = 1 << (h + nx), nh = 1 << (K - h);
+    for (int idx = c.tid; idx < nl + nh; idx += Ctx<T, K>::NT) {
+      const bool low = idx < nl;
+      const int e = low ? idx : idx - nl;
+      double ang = 0.0;
+      for (int ti = tbeg; ti < tend; ++ti) {
+        const DevTerm *tm = a.terms + ti;
+        const int tab_id = uni(tm->tab);
+        if (low ? (tab_id != 0) : (tab_id == 0)) continue;
+        const int nb = uni(tm->nbits);
+        int v = 0;
+        for (int q = 0; q < nb; ++q) {
+          int bit;
+          const int tb = uni(tm->tb[q]);
+          if (tb < 0) {
+            bit = (c.base >> uni(tm->gb[q])) & 1;
+          } else if (low) {
+            if (tb < h)
+              bit = (e >> tb) & 1;
+            else
+              bit = (e >> (h + (tb == ex0 ? 0 : (tb == ex1 ? 1 : 2)))) & 1;
+          } else {
+            bit = (e >> (tb - h)) & 1;
+          }
+          v = (v << 1) | bit;
+        }
+        const int ang_off = uni(tm->ang);
+        const double *an = uni(tm->per_sample) ? a.dbl_ps + (size_t)c.sample0 * a.dbl_ps_stride + ang_off
+                                               : a.dbl + ang_off;
+        ang += an[v];
+      }
+      double s, co;
+      sincos(ang, &s, &co);
+      tab[off + idx] = cmk<T>((T)co, (T)s);
+    }
+  }
+}
+
+// Split-table phase of tile element t.  The extra index bits are passed in
+// registers (x0..x2 = tile-bit positions, unused ones point at bit 31 of t,
+// which is always 0).
+struct DiagView {
+  int h, nx, lds_off, th_off, x0, x1, x2;
+};
+
+__device__ __forceinline__ DiagView diag_view(const DevDiag *dg) {
+  DiagView v;
+  v.h = uni(dg->h);
+  v.nx = uni(dg->n_extra);
+  v.lds_off = uni(dg->lds_off);
+  v.th_off = v.lds_off + (1 << (v.h + v.nx));
+  v.x0 = v.nx > 0 ? uni(dg->extra[0]) : 31;
+  v.x1 = v.nx > 1 ? uni(dg->extra[1]) : 31;
+  v.x2 = v.nx > 2 ? uni(dg->extra[2]) : 31;
+  return v;
+}
+
+template <typename T>
+__device__ __forceinline__ cplx<T> diag_phase(const DiagView &d, const cplx<T> *tab, int t) {
+  const int il = (t & ((1 << d.h) - 1)) | (((t >> d.x0) & 1) << d.h) | (((t >> d.x1) & 1) << (d.h + 1)) |
+                 (((t >> d.x2) & 1) << (d.h + 2));
+  return cmul(tab[d.lds_off + il], tab[d.th_off + (t >> d.h)]);
+}
+
+template <typename T, int K, bool BWD>
+__device__ __forceinline__ void run_stage(const Ctx<T, K> &c, const PassArgs<T> &a, const UStage &S, cplx<T> *Lp,
+                          cplx<T> *Ll, const cplx<T> *tab, bool grad_only) {
+  constexpr int NT = Ctx<T, K>::NT;
+  const int op0_kind = uni(a.ops[S.op_begin].kind);
+  if (op0_kind == OP_PERM) {
+    // in-tile permutation: forward new[t] = old[src(t)], backward the inverse
+    const DevPerm *pm = a.perms + uni(a.ops[S.op_begin].aux);
+    cplx<T> vp[NREG], vl[NREG];
+    int srcs[NREG];
+    uint32_t sthr = uniu(pm->cxor);
+    for (int b = 0; b < K - RB; ++b) {
+      const uint32_t col = uniu(pm->cols[b]);
+      if ((c.tid >> b) & 1) sthr ^= col;
+    }
+    uint32_t rcol[RB];
+#pragma unroll
+    for (int b = 0; b < RB; ++b) rcol[b] = uniu(pm->cols[K - RB + b]);
+#pragma unroll
+    for (int i = 0; i < NREG; ++i) {
+      const int t = c.tid + i * NT;
+      uint32_t s = sthr;
+#pragma unroll
+      for (int b = 0; b < RB; ++b)
+        if ((i >> b) & 1) s ^= rcol[b];
+      srcs[i] = (int)s;
+      const int rd = BWD ? t : (int)s;
+      vp[i] = Lp[swz<T>(rd)];
+      if (BWD) vl[i] = Ll[swz<T>(rd)];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < NREG; ++i) {
+      const int t = c.tid + i * NT;
+      const int wr = BWD ? srcs[i] : t;
+      Lp[swz<T>(wr)] = vp[i];
+      if (BWD) Ll[swz<T>(wr)] = vl[i];
+    }
+    __syncthreads();
+    return;
+  }
+  // thread tile base: the non-register tile bits, in increasing order, from tid
+  int tt = 0;
+  {
+    int cbit = 0;
+    for (int b = 0; b < K; ++b) {
+      const bool isreg = (b == S.rbits[0]) | (b == S.rbits[1]) | (b == S.rbits[2]) | (b == S.rbits[3]);
+      if (!isreg) {
+        tt |= ((c.tid >> cbit) & 1) << b;
+        ++cbit;
+      }
+    }
+  }
+  int toff[NREG], aoff[NREG];
+  {
+    const int o0 = 1 << S.rbits[0], o1 = 1 << S.rbits[1], o2 = 1 << S.rbits[2], o3 = 1 << S.rbits[3];
+    const int st = swz<T>(tt), s0 = swz<T>(o0), s1 = swz<T>(o1), s2 = swz<T>(o2), s3 = swz<T>(o3);
+#pragma unroll
+    for (int j = 0; j < NREG; ++j) {
+      toff[j] = tt | ((j & 1) ? o0 : 0) | ((j & 2) ? o1 : 0) | ((j & 4) ? o2 : 0) | ((j & 8) ? o3 : 0);
+      aoff[j] = st ^ ((j & 1) ? s0 : 0) ^ ((j & 2) ? s1 : 0) ^ ((j & 4) ? s2 : 0) ^ ((j & 8) ? s3 : 0);
+    }
+  }
+  cplx<T> vp[NREG], vl[NREG];
+#pragma unroll
+  for (int j = 0; j < NREG; ++j) {
+    vp[j] = Lp[aoff[j]];
+    if (BWD) vl[j] = Ll[aoff[j]];
+  }
+  const int s_thr = thread_sample(c, a.batch);
+  const int nops = S.op_end - S.op_begin;
+  for (int oi = 0; oi < nops; ++oi) {
+    const UOp op = load_op(a.ops + (BWD ? (S.op_end - 1 - oi) : (S.op_begin + oi)));
+    if (op.kind == OP_U1 || op.kind == OP_GRAD1) {
+      const cplx<T> *mg = op_mat(a, op, s_thr);
+      if (BWD && (op.flags & F_GRAD)) {
+        T sx = 0, sy = 0, sz = 0;
+        u1_grad_dispatch(vp, vl, op.r0, sx, sy, sz);
+        write_acc(c, a, sx, op.acc + 0);
+        write_acc(c, a, sy, op.acc + 1);
+        write_acc(c, a, sz, op.acc + 2);
+      }
+      if (op.kind == OP_U1) {
+        cplx<T> m[4];
+        m[0] = mg[0]; m[1] = mg[1]; m[2] = mg[2]; m[3] = mg[3];
+        u1_dispatch<T, BWD>(vp, m, op.r0, op.flags);
+        if (BWD) u1_dispatch<T, true>(vl, m, op.r0, op.flags);
+      }
+    } else if (op.kind == OP_U2) {
+      const cplx<T> *mg = op_mat(a, op, s_thr);
+      if (BWD && (op.flags & F_GRAD)) {
+        const T g = u2_grad_dispatch(vp, vl, op.r0, op.r1, op.aux);
+        write_acc(c, a, g, op.acc);
+      }
+      u2_dispatch<T, BWD>(vp, mg, op.r0, op.r1);
+      if (BWD) u2_dispatch<T, true>(vl, mg, op.r0, op.r1);
+    } else if (op.kind == OP_DIAG) {
+      const DevDiag *dg = a.diags + uni(a.pass->diag_begin) + op.aux;
+      const DiagView dv = diag_view(dg);
+      if (BWD && (op.flags & F_GRAD)) {
+        // w = Im(conj(l) p); parity sums over each term's bits via a register WHT
+        T w[NREG];
+#pragma unroll
+        for (int j = 0; j < NREG; ++j) w[j] = vl[j].x * vp[j].y - vl[j].y * vp[j].x;
+        wht16(w);
+        const int tbeg = uni(dg->term_begin), tend = uni(dg->term_end);
+        for (int ti = tbeg; ti < tend; ++ti) {
+          const DevTerm *tm = a.terms + ti;
+          const int tacc = uni(tm->acc);
+          if (tacc < 0) continue;
+          int m = 0;
+          int neg = 0;
+          const int nb = uni(tm->nbits);
+          for (int q = 0; q < nb; ++q) {
+            const int tb = uni(tm->tb[q]);
+            if (tb < 0) {
+              neg ^= (c.base >> uni(tm->gb[q])) & 1;
+            } else {
+              int rk = -1;
+              for (int k = 0; k < RB; ++k)
+                if (S.rbits[k] == tb) rk = k;
+              if (rk >= 0)
+                m |= 1 << rk;
+              else
+                neg ^= (tt >> tb) & 1;
+            }
+          }
+          T val = wht_pick(w, m);
+          if (neg) val = -val;
+          write_acc(c, a, val, tacc);
+        }
+      }
+#pragma unroll
+      for (int j = 0; j < NREG; ++j) {
+        cplx<T> d = diag_phase<T>(dv, tab, toff[j]);
+        if (BWD) d = cconj(d);
+        vp[j] = cmul(vp[j], d);
+        if (BWD) vl[j] = cmul(vl[j], d);
+      }
+    }
+  }
+  if (!grad_only) {
+#pragma unroll
+    for (int j = 0; j < NREG; ++j) {
+      Lp[aoff[j]] = vp[j];
+      if (BWD) Ll[aoff[j]] = vl[j];
+    }
+  }
+  __syncthreads();
+}
+
+template <typename T, int K, bool BWD>
+__global__ void __launch_bounds__(1 << (K - RB)) k_pass(PassArgs<T> a) {
+  constexpr int NT = 1 << (K - RB);
+  constexpr int NE = 1 << K;
+  extern __shared__ __align__(16) unsigned char smem[];
+  cplx<T> *Lp = reinterpret_cast<cplx<T> *>(smem);
+  cplx<T> *Ll = Lp + NE;
+  cplx<T> *tab = Lp + (BWD ? 2 : 1) * NE;
+  const DevPass *P = a.pass;
+
+  Ctx<T, K> c;
+  c.tid = threadIdx.x;
+  c.lane = threadIdx.x & 63;
+  c.n = uni(P->n);
+  c.nv = uni(P->nv);
+  c.multi = c.nv < K;
+  c.base = 0;
+  c.units_wg_base = 0;
+  const int wg = blockIdx.x;
+  if (!c.multi) {
+    const int tl = c.nv - K;
+    c.sample0 = wg >> tl;
+    const uint32_t tile = (uint32_t)wg & ((1u << tl) - 1u);
+    for (int r = 0; r < tl; ++r)
+      if ((tile >> r) & 1) c.base |= 1u << uni(P->rest[r]);
+    c.seg_log = (K - RB) < 6 ? (K - RB) : 6;
+    c.units_wg_base = (int)tile * (NT >> c.seg_log);
+  } else {
+    c.sample0 = wg << (K - c.nv);
+    const int tps = c.nv - RB;  // log2 threads per sample
+    c.seg_log = tps < 6 ? tps : 6;
+  }
+  const int n = c.n;
+  const long long sstride = 1ll << n;
+
+  if (uni(P->n_diag) > 0) build_diag_tables<T, K>(c, a, tab);
+
+  // ---------------- load ----------------
+  // Element e = tid + i * NT has tile index e; tile bits 0..K-RB-1 come from
+  // tid and the top RB bits from i.
+  uint32_t ptid = 0;
+  for (int b = 0; b < K - RB; ++b)
+    if ((c.tid >> b) & 1) ptid |= 1u << uni(P->tpos[b]);
+  const int load_mode = uni(P->load_mode);
+  const bool fwd_load_global = !BWD && load_mode == LOAD_GLOBAL;
+  const bool fwd_embed = !BWD && load_mode == LOAD_EMBED;
+  // map used for this direction's load and store
+  const int lmap = uni(BWD ? P->has_store_map : P->has_load_map);
+  const int smap = uni(BWD ? P->has_load_map : P->has_store_map);
+  const uint32_t *ltc = BWD ? P->store_tcol : P->load_tcol;
+  const uint32_t *lrc = BWD ? P->store_rcol : P->load_rcol;
+  const uint32_t lc = uniu(BWD ? P->store_c : P->load_c);
+  const uint32_t *stc = BWD ? P->load_tcol : P->store_tcol;
+  const uint32_t *src_ = BWD ? P->load_rcol : P->store_rcol;
+  const uint32_t sc = uniu(BWD ? P->load_c : P->store_c);
+  uint32_t lbase = lc, lthr = 0, sbase = sc, sthr = 0;
+  if (!c.multi) {
+    const int tl = c.nv - K;
+    const uint32_t tile = (uint32_t)wg & ((1u << tl) - 1u);
+    for (int r = 0; r < tl; ++r) {
+      const uint32_t l_ = uniu(lrc[r]), s_ = uniu(src_[r]);
+      if ((tile >> r) & 1) {
+        lbase ^= l_;
+        sbase ^= s_;
+      }
+    }
+    for (int b = 0; b < K - RB; ++b) {
+      const uint32_t l_ = uniu(ltc[b]), s_ = uniu(stc[b]);
+      if ((c.tid >> b) & 1) {
+        lthr ^= l_;
+        sthr ^= s_;
+      }
+    }
+  }
+
+  uint32_t treg[RB], lreg[RB], sreg[RB];
+#pragma unroll
+  for (int b = 0; b < RB; ++b) {
+    treg[b] = 1u << uni(P->tpos[K - RB + b]);
+    lreg[b] = uniu(ltc[K - RB + b]);
+    sreg[b] = uniu(stc[K - RB + b]);
+  }
+  const int embed_mat = uni(P->embed_mat), embed_ps = uni(P->embed_per_sample);
+
+  if (fwd_embed) {
+    // product state: amplitude = prod over wires of the wire's state component
+    if (!c.multi) {
+      const cplx<T> *em = embed_ps ? a.mats_ps + (size_t)c.sample0 * a.mats_ps_stride + embed_mat
+                                   : a.mats + embed_mat;
+      // base (rest) bits and thread bits
+      cplx<T> cth = cmk<T>(1, 0);
+      for (int r = 0; r < c.nv - K; ++r) {
+        const int p = uni(P->rest[r]);
+        const cplx<T> *m = em + 4 * (n - 1 - p);
+        cth = cmul(cth, ((c.base >> p) & 1) ? m[2] : m[0]);
+      }
+      for (int b = 0; b < K - RB; ++b) {
+        const int p = uni(P->tpos[b]);
+        const cplx<T> *m = em + 4 * (n - 1 - p);
+        cth = cmul(cth, ((c.tid >> b) & 1) ? m[2] : m[0]);
+      }
+      cplx<T> f[RB][2];
+#pragma unroll
+      for (int b = 0; b < RB; ++b) {
+        const int p = uni(P->tpos[K - RB + b]);
+        const cplx<T> *m = em + 4 * (n - 1 - p);
+        f[b][0] = m[0];
+        f[b][1] = m[2];
+      }
+#pragma unroll
+      for (int i = 0; i < NREG; ++i) {
+        cplx<T> v = cth;
+#pragma unroll
+        for (int b = 0; b < RB; ++b) v = cmul(v, f[b][(i >> b) & 1]);
+        Lp[swz<T>(c.tid + i * NT)] = v;
+      }
+    } else {
+#pragma unroll 4
+      for (int i = 0; i < NREG; ++i) {
+        const int t = c.tid + i * NT;
+        const int s = c.sample0 + (t >> c.nv);
+        const int j = t & ((1 << c.nv) - 1);
+        cplx<T> v = cmk<T>(0, 0);
+        if (s < a.batch && j < (1 << n)) {
+          const cplx<T> *em = embed_ps ? a.mats_ps + (size_t)s * a.mats_ps_stride + embed_mat
+                                       : a.mats + embed_mat;
+          v = cmk<T>(1, 0);
+          for (int p = 0; p < n; ++p) {
+            const cplx<T> *m = em + 4 * (n - 1 - p);
+            v = cmul(v, ((j >> p) & 1) ? m[2] : m[0]);
+          }
+        }
+        Lp[swz<T>(t)] = v;
+      }
+    }
+  } else if (fwd_load_global || BWD) {
+#pragma unroll
+    for (int i = 0; i < NREG; ++i) {
+      const int t = c.tid + i * NT;
+      cplx<T> vp = cmk<T>(0, 0), vl = cmk<T>(0, 0);
+      if (!c.multi) {
+        uint32_t k;
+        if (lmap) {
+          k = lbase ^ lthr;
+#pragma unroll
+          for (int b = 0; b < RB; ++b)
+            if ((i >> b) & 1) k ^= lreg[b];
+        } else {
+          k = c.base | ptid;
+#pragma unroll
+          for (int b = 0; b < RB; ++b)
+            if ((i >> b) & 1) k |= treg[b];
+        }
+        const long long g = (long long)c.sample0 * sstride + k;
+        vp = a.src0[g];
+        if (BWD) vl = a.src1[g];
+      } else {
+        const int s = c.sample0 + (t >> c.nv);
+        const int j = t & ((1 << c.nv) - 1);
+        if (s < a.batch && j < (1 << n)) {
+          const long long g = (long long)s * sstride + j;
+          vp = a.src0[g];
+          if (BWD) vl = a.src1[g];
+        }
+      }
+      Lp[swz<T>(t)] = vp;
+      if (BWD) Ll[swz<T>(t)] = vl;
+    }
+  }
+  __syncthreads();
+
+  // ---------------- stages ----------------
+  const int ns = uni(P->n_stages), sb = uni(P->stage_begin);
+  for (int si = 0; si < ns; ++si) {
+    const UStage S = load_stage(a.stages + sb + (BWD ? (ns - 1 - si) : si));
+    run_stage<T, K, BWD>(c, a, S, Lp, Ll, tab, false);
+  }
+  if (BWD) {
+    const int ng = uni(P->n_grad_stages), gsb = uni(P->grad_stage_begin);
+    for (int si = 0; si < ng; ++si) {
+      const UStage S = load_stage(a.stages + gsb + si);
+      run_stage<T, K, BWD>(c, a, S, Lp, Ll, tab, true);
+    }
+    if (uni(P->skip_bwd_store)) return;
+  }
+
+  // ---------------- store ----------------
+#pragma unroll
+  for (int i = 0; i < NREG; ++i) {
+    const int t = c.tid + i * NT;
+    const cplx<T> vp = Lp[swz<T>(t)];
+    cplx<T> vl;
+    if (BWD) vl = Ll[swz<T>(t)];
+    if (!c.multi) {
+      uint32_t k;
+      if (smap) {
+        k = sbase ^ sthr;
+#pragma unroll
+        for (int b = 0; b < RB; ++b)
+          if ((i >> b) & 1) k ^= sreg[b];
+      } else {
+        k = c.base | ptid;
+#pragma unroll
+        for (int b = 0; b < RB; ++b)
+          if ((i >> b) & 1) k |= treg[b];
+      }
+      const long long g = (long long)c.sample0 * sstride + k;
+      a.dst0[g] = vp;
+      if (BWD) a.dst1[g] = vl;
+    } else {
+      const int s = c.sample0 + (t >> c.nv);
+      const int j = t & ((1 << c.nv) - 1);
+      if (s < a.batch && j < (1 << n)) {
+        const long long g = (long long)s * sstride + j;
+        a.dst0[g] = vp;
+        if (BWD) a.dst1[g] = vl;
+      }
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// readout and adjoint init: tiles of 2^KE consecutive amplitudes of [B, 2^n]
+// ---------------------------------------------------------------------------
+constexpr int KE = 12;
+constexpr int NTE = 1 << (KE - RB);
+
+template <typename T>
+struct ReadArgs {
+  const cplx<T> *psi;
+  cplx<T> *lam;
+  const double *g;      // [B, n] upstream (adj init)
+  double *partials;     // expval: [B][units][KE+1]
+  int n, batch;
+};
+
+// Element layout of the readout kernels: a workgroup covers 2^KE consecutive
+// amplitudes of the (virtually padded) index space; thread tid holds the 16
+// consecutive amplitudes 16*tid .. 16*tid+15, so its register bits are state
+// bits 0..3 and every thread belongs to exactly one sample.
+struct RdCtx {
+  int nv, multi, tps_log;
+  long long sample0;
+  uint32_t jbase;
+};
+
+__device__ __forceinline__ RdCtx rd_ctx(int n) {
+  RdCtx c;
+  c.nv = n < RB ? RB : n;
+  c.multi = c.nv < KE;
+  if (c.multi) {
+    c.sample0 = (long long)blockIdx.x << (KE - c.nv);
+    c.jbase = 0;
+    c.tps_log = c.nv - RB;
+  } else {
+    const int tl = c.nv - KE;
+    c.sample0 = (long long)blockIdx.x >> tl;
+    c.jbase = (uint32_t)(blockIdx.x & ((1u << tl) - 1u)) << KE;
+    c.tps_log = KE - RB;
+  }
+  return c;
+}
+
+__device__ __forceinline__ bool rd_elem(const RdCtx &c, int n, int batch, int t, long long &g) {
+  long long s;
+  uint32_t j;
+  if (c.multi) {
+    s = c.sample0 + (t >> c.nv);
+    j = (uint32_t)t & ((1u << c.nv) - 1u);
+  } else {
+    s = c.sample0;
+    j = c.jbase | (uint32_t)t;
+  }
+  if (s >= batch || j >= (1u << n)) return false;
+  g = (s << n) | j;
+  return true;
+}
+
+// Per sample and tile: total probability and the signed sum over each tile bit.
+template <typename T>
+__global__ void __launch_bounds__(NTE) k_expval(ReadArgs<T> a) {
+  const int n = a.n;
+  const int tid = threadIdx.x;
+  const RdCtx c = rd_ctx(n);
+  double tot = 0.0;
+  double sr[RB];
+#pragma unroll
+  for (int b = 0; b < RB; ++b) sr[b] = 0.0;
+#pragma unroll
+  for (int i = 0; i < NREG; ++i) {
+    long long g;
+    double p = 0.0;
+    if (rd_elem(c, n, a.batch, tid * NREG + i, g)) {
+      const cplx<T> v = a.psi[g];
+      p = (double)v.x * (double)v.x + (double)v.y * (double)v.y;
+    }
+    tot += p;
+#pragma unroll
+    for (int b = 0; b < RB; ++b) sr[b] += ((i >> b) & 1) ? -p : p;
+  }
+  // values: 0 = total, 1 + b = signed sum over tile bit b (b < 4 from
+  // registers, b >= 4 from thread bit b - 4)
+  double vals[KE + 1];
+  vals[0] = tot;
+#pragma unroll
+  for (int b = 0; b < RB; ++b) vals[1 + b] = sr[b];
+#pragma unroll
+  for (int b = RB; b < KE; ++b) vals[1 + b] = ((tid >> (b - RB)) & 1) ? -tot : tot;
+  const int seg_log = c.tps_log < 6 ? c.tps_log : 6;
+#pragma unroll
+  for (int v = 0; v <= KE; ++v) vals[v] = seg_reduce(vals[v], seg_log);
+  const long long units = c.multi ? 1 : (1ll << (c.nv - KE));
+  const long long u = c.multi ? 0 : ((long long)blockIdx.x & (units - 1));
+  if (c.tps_log >= 6) {
+    // a sample spans whole waves: combine its waves through LDS
+    __shared__ double red[(NTE / 64) * (KE + 1)];
+    const int wave = tid >> 6;
+    if ((tid & 63) == 0)
+      for (int v = 0; v <= KE; ++v) red[wave * (KE + 1) + v] = vals[v];
+    __syncthreads();
+    const int wps = 1 << (c.tps_log - 6);          // waves per sample
+    const int spt = (NTE / 64) / wps;               // samples in this tile
+    if (tid < spt * (KE + 1)) {
+      const int sl = tid / (KE + 1), v = tid % (KE + 1);
+      double s = 0.0;
+      for (int w = 0; w < wps; ++w) s += red[(sl * wps + w) * (KE + 1) + v];
+      const long long smp = c.sample0 + sl;
+      if (smp < a.batch) a.partials[(smp * units + u) * (KE + 1) + v] = s;
+    }
+  } else if ((tid & ((1 << seg_log) - 1)) == 0) {
+    const long long smp = c.sample0 + (tid >> seg_log);
+    if (smp < a.batch)
+      for (int v = 0; v <= KE; ++v) a.partials[(smp * units + u) * (KE + 1) + v] = vals[v];
+  }
+}
+
+// expz[b, i] and norm[b] from the partials; wire i <-> state bit p = n-1-i.
+__global__ void k_expval_final(const double *partials, double *expz, double *norm, int n, int batch) {
+  const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= batch * (n + 1)) return;
+  const int b = idx / (n + 1), i = idx % (n + 1);
+  const long long units = n > KE ? (1ll << (n - KE)) : 1;
+  double s = 0.0;
+  if (i == n) {
+    for (long long u = 0; u < units; ++u) s += partials[((long long)b * units + u) * (KE + 1)];
+    if (norm) norm[b] = s;
+    return;
+  }
+  const int p = n - 1 - i;
+  for (long long u = 0; u < units; ++u) {
+    const double *q = partials + ((long long)b * units + u) * (KE + 1);
+    if (p < KE)
+      s += q[1 + p];
+    else
+      s += ((u >> (p - KE)) & 1) ? -q[0] : q[0];
+  }
+  expz[(long long)b * n + i] = s;
+}
+
+// lambda = psi * h with h(j) = sum_i g_i (1 - 2 b_i(j)), per sample
+template <typename T>
+__global__ void __launch_bounds__(NTE) k_adj_init(ReadArgs<T> a) {
+  const int n = a.n;
+  const int tid = threadIdx.x;
+  const RdCtx c = rd_ctx(n);
+  // thread part: state bits >= 4 of the thread's elements
+  long long g0;
+  const bool any = rd_elem(c, n, a.batch, tid * NREG, g0);
+  if (!any && c.multi) {
+    // the thread's first element is padding or past the batch; so are the rest
+    return;
+  }
+  const long long s = g0 >> n;
+  const double *gg = a.g + s * n;
+  const uint32_t j0 = (uint32_t)(g0 & ((1ll << n) - 1));
+  double hthr = 0.0;
+  for (int p = RB; p < n; ++p) hthr += ((j0 >> p) & 1) ? -gg[n - 1 - p] : gg[n - 1 - p];
+#pragma unroll
+  for (int i = 0; i < NREG; ++i) {
+    long long g;
+    if (!rd_elem(c, n, a.batch, tid * NREG + i, g)) continue;
+    double h = hthr;
+#pragma unroll
+    for (int p = 0; p < RB; ++p)
+      if (p < n) h += ((i >> p) & 1) ? -gg[n - 1 - p] : gg[n - 1 - p];
+    const cplx<T> v = a.psi[g];
+    a.lam[g] = cmk<T>((T)(v.x * h), (T)(v.y * h));
+  }
+}
+
+// A[acc][b] = sum of the pass partials of sample b (FP64, fixed order)
+template <typename T>
+__global__ void k_acc_reduce(const T *partials, const long long *acc_static, const int *acc_units,
+                             int n_acc, int batch, double *A) {
+  const long long idx = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= (long long)n_acc * batch) return;
+  const int acc = (int)(idx / batch), b = (int)(idx % batch);
+  const int U = acc_units[acc];
+  const T *p = partials + acc_static[acc] * batch + (long long)b * U;
+  double s = 0.0;
+  for (int u = 0; u < U; ++u) s += (double)p[u];
+  A[idx] = s;
+}
+
+// gradients: weights sum over samples; features per sample
+__global__ void k_grad_combine(const int *cptr, const Contrib *contribs, const double *A,
+                               const double *dbl, const double *dbl_ps, int dbl_ps_stride, int n_w,
+                               int n_x, int batch, double *gw, double *gx) {
+  const long long idx = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx < n_w) {
+    const int p = (int)idx;
+    double s = 0.0;
+    for (int b = 0; b < batch; ++b)
+      for (int ci = cptr[p]; ci < cptr[p + 1]; ++ci) {
+        const Contrib cb = contribs[ci];
+        const double *co = cb.coef_ps ? dbl_ps + (size_t)b * dbl_ps_stride + cb.coef : dbl + cb.coef;
+        for (int k = 0; k < cb.n; ++k) s += co[k] * A[(long long)(cb.acc + k) * batch + b];
+      }
+    if (gw) gw[p] = s;
+    return;
+  }
+  const long long j = idx - n_w;
+  if (j >= (long long)n_x * batch || !gx) return;
+  const int b = (int)(j / n_x), f = (int)(j % n_x);
+  const int p = n_w + f;
+  double s = 0.0;
+  for (int ci = cptr[p]; ci < cptr[p + 1]; ++ci) {
+    const Contrib cb = contribs[ci];
+    const double *co = cb.coef_ps ? dbl_ps + (size_t)b * dbl_ps_stride + cb.coef : dbl + cb.coef;
+    for (int k = 0; k < cb.n; ++k) s += co[k] * A[(long long)(cb.acc + k) * batch + b];
+  }
+  gx[(long long)b * n_x + f] = s;
+}
+
+}  // namespace tqs

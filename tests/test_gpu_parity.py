@@ -1,0 +1,197 @@
+"""Parity of the HIP path with the CPU oracle, element by element.
+
+Every case builds a circuit through the C ABI (via the thin binding), runs
+forward, <Z_i> and the adjoint gradient on the GPU, and compares with the
+oracle's complex128 results at the tolerances in tests/gpu_util.py.
+"""
+import numpy as np
+import pytest
+import torch
+
+import workloads as W
+from oracle import sim
+from tests.gpu_util import compare, gpu_run, note, oracle_run
+
+pytestmark = pytest.mark.gpu
+
+if torch.cuda.is_available():
+    from paper_2506_04891_amd import tqsim as T
+
+
+def _circuit(n, layers, dtype, mode="auto", tile_bits=0):
+    return T.Circuit(n, layers, dtype, mode=mode, tile_bits=tile_bits)
+
+
+def _params(n, layers, B, seed, dist="normal"):
+    w, x = W.draw_params(n, layers, B, dist, seed)
+    g = W.upstream(B, n, "normal", seed)
+    return w, x, g
+
+
+LAYER_KINDS = [
+    ("RX", "ALL", "WEIGHT"), ("RY", "ALL", "WEIGHT"), ("RZ", "ALL", "WEIGHT"),
+    ("H", "ALL"), ("X", "ALL"), ("Z", "ALL"), ("S", "ALL"), ("SX", "ALL"),
+    ("GPI", "ALL", "WEIGHT"), ("GPI2", "ALL", "WEIGHT"), ("RZ", "ALL", "INPUT"),
+    ("CNOT", "RING"), ("CNOT", "CHAIN"), ("CZ", "RING"), ("SWAP", "CHAIN"),
+    ("ZZ", "RING", "WEIGHT"), ("ZZ", "CHAIN", "WEIGHT"), ("ZZ", "RING", "INPUT"),
+    ("MS", "PAIRS_EVEN", "WEIGHT"), ("MS", "PAIRS_ODD", "WEIGHT"),
+    ("ECR", "PAIRS_EVEN"), ("ECR", "PAIRS_ODD"), ("CNOT", "PAIRS_ODD"),
+]
+
+
+def _sandwich(n, spec):
+    """Embedding, an entangler (so the layer under test is not folded into the
+    product state), the layer under test, then a rotation layer so that its
+    parameters reach the <Z> readout."""
+    b = W._Builder(n)
+    b.add("RY", "ALL", "INPUT").add("RX", "ALL", "WEIGHT").add("CNOT", "CHAIN")
+    b.add(*spec[:3]) if len(spec) == 3 else b.add(*spec)
+    b.add("RX", "ALL", "WEIGHT").add("CZ", "CHAIN").add("RY", "ALL", "WEIGHT")
+    return b.layers
+
+
+@pytest.mark.parametrize("mode", ["per_layer", "fused"])
+@pytest.mark.parametrize("n", [2, 5, 6, 13, 14])
+@pytest.mark.parametrize("spec", LAYER_KINDS, ids=["-".join(s) for s in LAYER_KINDS])
+def test_layer_kind_c64(spec, n, mode):
+    if "PAIRS" in spec[1] and n % 2:
+        pytest.skip("brick pairs need even n")
+    layers = _sandwich(n, spec)
+    B = 3
+    w, x, g = _params(n, layers, B, seed=n)
+    note(f"case layer={spec} n={n} mode={mode} c64")
+    got = gpu_run(_circuit(n, layers, "c64", mode), w, x, g)
+    ref = oracle_run(n, layers, w, x, g)
+    compare(got, ref, "c64", label=f"{spec} n={n} {mode}")
+
+
+@pytest.mark.parametrize("mode", ["per_layer", "fused"])
+@pytest.mark.parametrize("n", [3, 6, 12])
+@pytest.mark.parametrize("spec", LAYER_KINDS, ids=["-".join(s) for s in LAYER_KINDS])
+def test_layer_kind_c128(spec, n, mode):
+    if "PAIRS" in spec[1] and n % 2:
+        pytest.skip("brick pairs need even n")
+    layers = _sandwich(n, spec)
+    B = 2
+    w, x, g = _params(n, layers, B, seed=100 + n)
+    note(f"case layer={spec} n={n} mode={mode} c128")
+    got = gpu_run(_circuit(n, layers, "c128", mode), w, x, g)
+    ref = oracle_run(n, layers, w, x, g)
+    compare(got, ref, "c128", label=f"{spec} n={n} {mode}")
+
+
+@pytest.mark.parametrize("tile_bits", [10, 11, 12])
+@pytest.mark.parametrize("name,builder,dist", [
+    ("rot_ring_zz", lambda n: W.circuit_rot_ring(n, 3, "RX", ("RX", "RY", "RZ"), zz=True), "normal"),
+    ("ionq", lambda n: W.circuit_ionq(n, 4), "uniform2pi"),
+    ("ibm", lambda n: W.circuit_ibm(n, 4), "uniform2pi"),
+])
+@pytest.mark.parametrize("n", [11, 12, 14])
+@pytest.mark.parametrize("mode", ["per_layer", "fused"])
+def test_config_shapes_multipass(name, builder, dist, n, tile_bits, mode):
+    if name in ("ionq", "ibm") and n % 2:
+        pytest.skip("brick pairs need even n")
+    layers = builder(n)
+    B = 3
+    w, x, g = _params(n, layers, B, seed=7, dist=dist)
+    note(f"case {name} n={n} K={tile_bits} mode={mode}")
+    got = gpu_run(_circuit(n, layers, "c64", mode, tile_bits), w, x, g)
+    ref = oracle_run(n, layers, w, x, g)
+    compare(got, ref, "c64", label=f"{name} n={n} K={tile_bits} {mode}")
+
+
+def test_config1_exact():
+    """4 qubits, batch 16, complex128: every output against the oracle at 1e-12."""
+    n, B, dt, layers, w, x = W.config("c1_4q_b16")
+    g = W.upstream(B, n, "normal", 1)
+    for mode in ("per_layer", "fused"):
+        note(f"case c1 mode={mode}")
+        got = gpu_run(_circuit(n, layers, dt, mode), w, x, g)
+        ref = oracle_run(n, layers, w, x, g)
+        compare(got, ref, "c128", label=f"c1 {mode}")
+        np.testing.assert_allclose(got["norm"], 1.0, atol=1e-13)
+
+
+@pytest.mark.parametrize("B", [1, 5, 17, 64, 65])
+@pytest.mark.parametrize("n", [1, 2, 4, 7, 9])
+def test_small_n_batches(n, B):
+    """Several samples per workgroup, ragged last workgroup, virtual padding for n < 4."""
+    layers = W.circuit_rot_ring(n, 2, "RY", ("RY", "RZ"))
+    w, x, g = _params(n, layers, B, seed=B + 10 * n)
+    note(f"case small n={n} B={B}")
+    got = gpu_run(_circuit(n, layers, "c64"), w, x, g)
+    ref = oracle_run(n, layers, w, x, g)
+    compare(got, ref, "c64", label=f"small n={n} B={B}")
+
+
+def test_ghz_and_bell():
+    for n in (2, 3, 6, 13):
+        layers = [W.L("H", "WIRE", wire=0), W.L("CNOT", "CHAIN")]
+        c = _circuit(n, layers, "c128")
+        note(f"case ghz n={n}")
+        got = gpu_run(c, np.zeros(0), np.zeros((1, 0)), batch=1)
+        ref = np.zeros(2 ** n, dtype=complex)
+        ref[0] = ref[-1] = 1 / np.sqrt(2)
+        np.testing.assert_allclose(got["psi"][0], ref, atol=1e-15)
+        np.testing.assert_allclose(got["e"][0], 0.0, atol=1e-15)
+
+
+def test_ry_embedding_closed_form():
+    for n in (1, 4, 12, 14):
+        layers = [W.L("RY", "ALL", "INPUT")]
+        x = np.random.default_rng(n).uniform(-np.pi, np.pi, (4, n))
+        c = _circuit(n, layers, "c128")
+        note(f"case ry-embed n={n}")
+        got = gpu_run(c, np.zeros(0), x, np.ones((4, n)))
+        np.testing.assert_allclose(got["e"], np.cos(x), atol=1e-13)
+        np.testing.assert_allclose(got["gx"], -np.sin(x), atol=1e-12)
+
+
+def test_deterministic_repeat():
+    n, B, dt, layers, w, x = W.config("c4a_16q_b128_ionq")
+    n = 14
+    layers = W.circuit_ionq(n, 8)
+    w, x = W.draw_params(n, layers, 8, "uniform2pi", 4)
+    g = W.upstream(8, n, "normal", 2)
+    c = _circuit(n, layers, "c64")
+    a = gpu_run(c, w, x, g)
+    b = gpu_run(c, w, x, g)
+    for k in ("psi", "e", "gw", "gx"):
+        np.testing.assert_array_equal(a[k], b[k])
+
+
+# ---------------------------------------------------------------- full size --
+
+def _sampled_full(name, samples):
+    n, B, dt, layers, w, x = W.config(name)
+    g = np.zeros((B, n))
+    g[samples] = W.upstream(len(samples), n, "normal", 9)
+    note(f"case full {name} samples={samples}")
+    got = gpu_run(_circuit(n, layers, dt), w, x, g)
+    # the oracle computes only the sampled rows; weight gradients only receive
+    # contributions from samples with a nonzero upstream gradient
+    ref = oracle_run(n, layers, w, x[samples], g[samples])
+    np.testing.assert_allclose(got["e"][samples], ref["e"], atol=2e-5)
+    np.testing.assert_allclose(got["norm"], 1.0, atol=1e-5)
+    e1 = np.max(np.abs(got["gw"] - ref["gw"])) / np.max(np.abs(ref["gw"]))
+    e2 = np.max(np.abs(got["gx"][samples] - ref["gx"])) / np.max(np.abs(ref["gx"]))
+    assert e1 <= 1e-4 and e2 <= 1e-4, (e1, e2)
+    others = [b for b in range(B) if b not in samples]
+    np.testing.assert_array_equal(got["gx"][others], 0.0)
+    return got
+
+
+def test_full_c2_sampled():
+    _sampled_full("c2_12q_b256", [0, 97, 255])
+
+
+def test_full_c4a_sampled():
+    _sampled_full("c4a_16q_b128_ionq", [0, 127])
+
+
+def test_full_c4b_sampled():
+    _sampled_full("c4b_16q_b128_ibm", [5, 64])
+
+
+def test_full_c3_sampled():
+    _sampled_full("c3_20q_b32", [31])
