@@ -1,0 +1,191 @@
+#!/usr/bin/env python3
+"""Benchmark: forward + adjoint-backward circuit evaluations per second at
+16 qubits, batch 128, complex64, on the IonQ-style and IBM-style native-gate
+circuits (one step = both circuits, forward <Z_i> and adjoint gradients of all
+weights and features, for the whole batch).
+
+Prints one JSON line.  Besides the headline value it reports the roofline of
+the dominant kernel (HIP-event durations measured inside this run), the same
+figures for the 20-qubit rotation + ZZ + CNOT-ring circuit (where the state
+set exceeds the on-chip caches), and the CPU oracle timed on a bounded sample.
+"""
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+# FP32 vector peak without packed FP32 instructions (the kernels are built
+# without them): 256 CUs x 4 SIMDs x 16 lanes x 2 flop/FMA x 2.4 GHz.
+VALU_FP32_PEAK_TFLOPS = 256 * 4 * 16 * 2 * 2.4e9 / 1e12
+BALANCE = VALU_FP32_PEAK_TFLOPS * 1e12 / (HBM_PEAK_GBS * 1e9)   # flop per byte
+
+
+def parse():
+    p = argparse.ArgumentParser()
+    p.add_argument("--gpus", type=int, default=1)
+    p.add_argument("--steps", type=int, default=20)
+    p.add_argument("--warmup", type=int, default=5)
+    p.add_argument("--no-cpu-baseline", action="store_true")
+    p.add_argument("--no-20q", action="store_true")
+    p.add_argument("--mode", default="auto", choices=["auto", "per_layer", "fused"])
+    return p.parse_args()
+
+
+def roofline(report, traffic=None):
+    """Roofline object of the kernel kind with the largest total time."""
+    kinds = {k: v for k, v in report.items() if v["count"] > 0}
+    name = max(kinds, key=lambda k: kinds[k]["ms"])
+    r = kinds[name]
+    sec = r["ms"] / 1e3
+    intensity = r["flops"] / max(r["bytes"], 1.0)
+    if intensity > BALANCE:
+        achieved = r["flops"] / sec / 1e12
+        out = {"bound": "alu", "achieved": round(achieved, 3), "peak": round(VALU_FP32_PEAK_TFLOPS, 1),
+               "unit": "TFLOP/s", "frac": round(achieved / VALU_FP32_PEAK_TFLOPS, 4)}
+    else:
+        achieved = r["bytes"] / sec / 1e9
+        out = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+               "frac": round(achieved / HBM_PEAK_GBS, 4)}
+    out.update({"traffic": traffic, "kernel": name, "launches": r["count"],
+                "avg_launch_us": round(r["ms"] * 1e3 / r["count"], 2),
+                "bytes_per_launch": r["bytes"] / r["count"], "flops_per_launch": r["flops"] / r["count"],
+                "hbm_GBps": round(r["bytes"] / sec / 1e9, 1),
+                "valu_TFLOPs": round(r["flops"] / sec / 1e12, 3)})
+    return out
+
+
+class Job:
+    """One circuit at its full batch, device tensors resident in HBM."""
+
+    def __init__(self, name, mode):
+        import torch
+        import workloads as W
+        from paper_2506_04891_amd import tqsim as T
+        n, B, dt, layers, w, x = W.config(name)
+        self.name, self.n, self.B = name, n, B
+        self.circ = T.Circuit(n, layers, dt, mode=mode)
+        dev = torch.device("cuda")
+        self.w = torch.tensor(w, device=dev)
+        self.x = torch.tensor(x, device=dev)
+        self.g = torch.tensor(W.upstream(B, n, "ones"), device=dev)
+        self.state = torch.empty((B, 2 ** n), dtype=self.circ.complex_dtype, device=dev)
+        self.ws = self.circ.workspace(B, True, dev)
+
+    def step(self):
+        c = self.circ
+        c.forward(self.w, self.x, state=self.state, ws=self.ws)
+        self.e = c.expval_z(self.state, ws=self.ws)
+        self.gw, self.gx = c.adjoint_grad(self.w, self.x, self.state, self.g, ws=self.ws)
+
+
+def time_jobs(jobs, steps, warmup):
+    import torch
+    for _ in range(warmup):
+        for j in jobs:
+            j.step()
+    torch.cuda.synchronize()
+    for j in jobs:
+        j.circ.profile_report(reset=True)
+        j.circ.set_profile(True)
+    t0 = torch.cuda.Event(enable_timing=True)
+    t1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    wall0 = time.perf_counter()
+    t0.record()
+    for _ in range(steps):
+        for j in jobs:
+            j.step()
+    t1.record()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - wall0
+    ms = t0.elapsed_time(t1) / steps
+    merged = {}
+    for j in jobs:
+        j.circ.set_profile(False)
+        for k, v in j.circ.profile_report(reset=True).items():
+            m = merged.setdefault(k, {"count": 0, "ms": 0.0, "bytes": 0.0, "flops": 0.0})
+            for f in m:
+                m[f] += v[f]
+    return ms, wall / steps * 1e3, merged
+
+
+def cpu_baseline(sample=2):
+    """The oracle (numpy complex128, per-gate contraction) on `sample` samples
+    of each 16-qubit circuit: forward <Z_i> and adjoint gradients."""
+    import numpy as np
+    import workloads as W
+    from oracle import sim
+    t = 0.0
+    evals = 0
+    for name in ("c4a_16q_b128_ionq", "c4b_16q_b128_ibm"):
+        n, B, dt, layers, w, x = W.config(name)
+        xs = x[:sample]
+        g = W.upstream(sample, n, "ones")
+        t0 = time.perf_counter()
+        sim.grad_adjoint(n, layers, w, xs, g)
+        t += time.perf_counter() - t0
+        evals += sample
+    return {"value": round(evals / t, 3), "unit": "circuit evals/s", "cores": 1, "kind": "oracle",
+            "sample": f"{sample} samples of each 16-qubit circuit (IonQ and IBM gate sets), forward + "
+                      f"adjoint in numpy complex128 on one host thread; {round(t, 2)} s; host has "
+                      f"{os.cpu_count()} logical CPUs"}
+
+
+def main():
+    a = parse()
+    if a.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1", "n_gpus": a.gpus}))
+        sys.exit(2)
+    import torch
+    if not torch.cuda.is_available():
+        print(json.dumps({"error": "no GPU visible"}))
+        sys.exit(1)
+    from paper_2506_04891_amd import tqsim as T
+    T.lib()   # fails loudly when the HIP library is missing
+
+    jobs = [Job("c4a_16q_b128_ionq", a.mode), Job("c4b_16q_b128_ibm", a.mode)]
+    ms, wall_ms, rep = time_jobs(jobs, a.steps, a.warmup)
+    evals = sum(j.B for j in jobs)
+    value = evals / (ms / 1e3)
+    out = {
+        "metric": "fwd+bwd circuit evals/s @16q batch128",
+        "value": round(value, 1),
+        "unit": "circuit evals/s",
+        "n_gpus": 1,
+        "steps": a.steps,
+        "warmup": a.warmup,
+        "ms_per_step": round(ms, 4),
+        "wall_ms_per_step": round(wall_ms, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "c64 (f32 state, f64 reductions)",
+        "data": "synthetic (seeded weights U(0,2pi), features U(-pi,pi), upstream dL/d<Z>=1)",
+        "config": {"workload": "16 qubits, batch 128, complex64: IonQ GPI/GPI2/MS and IBM RZ/SX/ECR "
+                               "native-gate circuits, 8 blocks each, forward <Z_i> + adjoint gradients",
+                   "n_qubits": 16, "batch": 128, "circuits": [j.name for j in jobs],
+                   "mode": a.mode, "passes": {j.name: len(j.circ.plan()["passes"]) for j in jobs}},
+        "roofline": roofline(rep),
+        "kernels": {k: {"count": v["count"], "ms_per_step": round(v["ms"] / a.steps, 4)} for k, v in rep.items()},
+    }
+    if not a.no_20q:
+        j20 = Job("c3_20q_b32", a.mode)
+        ms20, _, rep20 = time_jobs([j20], max(3, a.steps // 4), 2)
+        out["q20"] = {"workload": "20 qubits, batch 32, complex64: RX embedding + 6 x [RX, RY, RZ, ZZ ring, "
+                                  "CNOT ring], forward <Z_i> + adjoint gradients",
+                      "evals_per_s": round(j20.B / (ms20 / 1e3), 1), "ms_per_step": round(ms20, 3),
+                      "roofline": roofline(rep20),
+                      "kernels": {k: {"count": v["count"], "ms": round(v["ms"], 3)} for k, v in rep20.items()}}
+        del j20
+    out["cpu_baseline"] = None if a.no_cpu_baseline else cpu_baseline()
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

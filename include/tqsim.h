@@ -153,8 +153,17 @@ tqs_status tqs_adjoint_grad(tqs_circuit *c, int32_t batch, const double *weights
  *   "mode"       0 = auto, 1 = per-layer passes (one technique per layer),
  *                2 = fused passes, 3 = dense (full layer unitaries, n <= 8)
  *   "tile_bits"  0 = auto, else K in [10, 12] for multi-pass plans
- * EINVAL for an unknown key or value, or after the plan has been uploaded. */
+ *   "profile"    1 = time every kernel launch with HIP events (any time; not
+ *                to be used while the stream is being captured into a graph)
+ * EINVAL for an unknown key or value, or for a plan key after the plan has
+ * been uploaded. */
 tqs_status tqs_set_option(tqs_circuit *c, const char *key, int64_t value);
+
+/* Per-kernel-kind launch statistics gathered while "profile" is on: waits for
+ * the recorded events, then writes JSON {kind: {count, ms, bytes, flops}} where
+ * bytes / flops are the algorithmic HBM bytes and arithmetic of the launches.
+ * reset != 0 clears the statistics afterwards. */
+tqs_status tqs_profile_report(tqs_circuit *c, int32_t reset, char *buf, size_t len);
 
 /* JSON description of the execution plan (passes, tiles, stages, kernels). */
 tqs_status tqs_plan_describe(const tqs_circuit *c, char *buf, size_t len);

@@ -57,6 +57,25 @@ __device__ __forceinline__ cplx<T> cfma2(cplx<T> m, cplx<T> a, cplx<T> n, cplx<T
   return r;
 }
 
+// Plan tables, gate matrices and angles are read-only while a pass runs; they
+// are addressed through the constant address space so that wave-uniform reads
+// become scalar (SMEM) loads through the scalar cache.
+#define TQS_CONST __attribute__((address_space(4)))
+template <typename X>
+using kptr = const TQS_CONST X *;
+template <typename X>
+__host__ __device__ __forceinline__ kptr<X> kc(const X *p) {
+  return (kptr<X>)(uintptr_t)p;
+}
+
+template <typename T>
+__device__ __forceinline__ cplx<T> kld(kptr<cplx<T>> p, long long i) {
+  cplx<T> r;
+  r.x = p[i].x;
+  r.y = p[i].y;
+  return r;
+}
+
 // LDS swizzle: XOR-fold the higher index groups into the lowest group so that
 // 16 (8-byte) or 8 (16-byte) lanes walking any four / three distinct bit
 // classes hit distinct banks.  GF(2)-linear, so swz(a ^ b) = swz(a) ^ swz(b).
@@ -81,7 +100,7 @@ __device__ __forceinline__ uint32_t uniu(uint32_t x) {
 struct UOp {
   int kind, flags, r0, r1, mat, acc, aux;
 };
-__device__ __forceinline__ UOp load_op(const DevOp *p) {
+__device__ __forceinline__ UOp load_op(kptr<DevOp> p) {
   UOp o;
   o.kind = uni(p->kind);
   o.flags = uni(p->flags);
@@ -96,7 +115,7 @@ struct UStage {
   int rbits[RB];
   int op_begin, op_end;
 };
-__device__ __forceinline__ UStage load_stage(const DevStage *p) {
+__device__ __forceinline__ UStage load_stage(kptr<DevStage> p) {
   UStage s;
   s.rbits[0] = uni(p->rbits[0]);
   s.rbits[1] = uni(p->rbits[1]);
@@ -277,8 +296,8 @@ __device__ __forceinline__ void mat2mul_dag(const zd a[4], const zd b[4], zd r[4
 
 template <typename T>
 struct PrepArgs {
-  const PrepItem *items;
-  const Factor *factors;
+  kptr<PrepItem> items;
+  kptr<Factor> factors;
   int n_items;
   const double *w;
   const double *x;
@@ -292,12 +311,31 @@ struct PrepArgs {
   int dbl_ps_stride;
 };
 
+__device__ __forceinline__ PrepItem ld_item(kptr<PrepItem> p) {
+  PrepItem r;
+  r.kind = p->kind;
+  r.per_sample = p->per_sample;
+  r.out = p->out;
+  r.f_begin = p->f_begin;
+  r.f_end = p->f_end;
+  r.k = p->k;
+  return r;
+}
+__device__ __forceinline__ Factor ld_factor(kptr<Factor> p) {
+  Factor f;
+  f.gate = p->gate;
+  f.src = p->src;
+  f.pidx = p->pidx;
+  f.fixed = p->fixed;
+  return f;
+}
+
 template <typename T>
 __global__ void __launch_bounds__(64) k_prep(PrepArgs<T> a) {
   const int item = blockIdx.y;
   const int b = blockIdx.x * 64 + threadIdx.x;
   if (item >= a.n_items) return;
-  const PrepItem it = a.items[item];
+  const PrepItem it = ld_item(a.items + item);
   if (it.per_sample ? (b >= a.batch) : (b != 0)) return;
   const int bs = it.per_sample ? b : 0;
   switch (it.kind) {
@@ -305,7 +343,7 @@ __global__ void __launch_bounds__(64) k_prep(PrepArgs<T> a) {
       zd m[4], d[4], f[4];
       m[0] = zmk(1, 0); m[1] = zmk(0, 0); m[2] = zmk(0, 0); m[3] = zmk(1, 0);
       for (int k = it.f_begin; k < it.f_end; ++k) {
-        const Factor fc = a.factors[k];
+        const Factor fc = ld_factor(a.factors + (k));
         gate2(fc.gate, factor_param(fc, a.w, a.x, a.nfeat, bs), f, d);
         mat2mul(f, m, m);
       }
@@ -315,7 +353,7 @@ __global__ void __launch_bounds__(64) k_prep(PrepArgs<T> a) {
     }
     case PREP_MAT2: {
       zd m[16];
-      const Factor fc = a.factors[it.f_begin];
+      const Factor fc = ld_factor(a.factors + (it.f_begin));
       gate4(fc.gate, factor_param(fc, a.w, a.x, a.nfeat, bs), m);
       cplx<T> *o = it.per_sample ? a.mats_ps + (size_t)bs * a.mats_ps_stride + it.out : a.mats + it.out;
       for (int i = 0; i < 16; ++i) o[i] = cmk<T>((T)m[i].x, (T)m[i].y);
@@ -323,7 +361,7 @@ __global__ void __launch_bounds__(64) k_prep(PrepArgs<T> a) {
     }
     case PREP_ANG: {
       double ang[4], da[4];
-      const Factor fc = a.factors[it.f_begin];
+      const Factor fc = ld_factor(a.factors + (it.f_begin));
       int nb = diag_angles(fc.gate, factor_param(fc, a.w, a.x, a.nfeat, bs), ang, da);
       double *o = it.per_sample ? a.dbl_ps + (size_t)bs * a.dbl_ps_stride + it.out : a.dbl + it.out;
       for (int i = 0; i < (1 << nb); ++i) o[i] = ang[i];
@@ -332,13 +370,13 @@ __global__ void __launch_bounds__(64) k_prep(PrepArgs<T> a) {
     case PREP_COEF1: {
       // h = V G V^dag with G = i dF F^dag of factor k and V the later factors.
       zd f[4], d[4], g[4], v[4], tmp[4];
-      const Factor fk = a.factors[it.k];
+      const Factor fk = ld_factor(a.factors + (it.k));
       gate2(fk.gate, factor_param(fk, a.w, a.x, a.nfeat, bs), f, d);
       mat2mul_dag(d, f, g);
       for (int i = 0; i < 4; ++i) g[i] = zmul(zmk(0, 1), g[i]);
       v[0] = zmk(1, 0); v[1] = zmk(0, 0); v[2] = zmk(0, 0); v[3] = zmk(1, 0);
       for (int k = it.k + 1; k < it.f_end; ++k) {
-        const Factor fc = a.factors[k];
+        const Factor fc = ld_factor(a.factors + (k));
         gate2(fc.gate, factor_param(fc, a.w, a.x, a.nfeat, bs), f, d);
         mat2mul(f, v, v);
       }
@@ -359,7 +397,7 @@ __global__ void __launch_bounds__(64) k_prep(PrepArgs<T> a) {
     }
     case PREP_COEFD: {
       double ang[4], da[4];
-      const Factor fc = a.factors[it.f_begin];
+      const Factor fc = ld_factor(a.factors + (it.f_begin));
       int nb = diag_angles(fc.gate, factor_param(fc, a.w, a.x, a.nfeat, bs), ang, da);
       // dL/dtheta = -2 sum_v dphi(v) W(v) with W(v) = class sum; only the
       // parity sum over all term bits has a nonzero weight for these gates.
@@ -429,9 +467,9 @@ __device__ __forceinline__ void u1_grad(const cplx<T> (&p)[NREG], const cplx<T> 
 }
 
 template <typename T, int R0, int R1, bool ADJ>
-__device__ __forceinline__ void u2_apply(cplx<T> (&v)[NREG], const cplx<T> *__restrict__ mg) {
+__device__ __forceinline__ void u2_apply(cplx<T> (&v)[NREG], kptr<cplx<T>> mg) {
   // entry (r, c) of the applied matrix: U[r][c], or conj(U[c][r]) for the adjoint
-#define TQS_M(r, c) (ADJ ? cconj(mg[(c) * 4 + (r)]) : mg[(r) * 4 + (c)])
+#define TQS_M(r, c) (ADJ ? cconj(kld(mg, (c) * 4 + (r))) : kld(mg, (r) * 4 + (c)))
   const cplx<T> m00 = TQS_M(0, 0), m01 = TQS_M(0, 1), m02 = TQS_M(0, 2), m03 = TQS_M(0, 3);
   const cplx<T> m10 = TQS_M(1, 0), m11 = TQS_M(1, 1), m12 = TQS_M(1, 2), m13 = TQS_M(1, 3);
   const cplx<T> m20 = TQS_M(2, 0), m21 = TQS_M(2, 1), m22 = TQS_M(2, 2), m23 = TQS_M(2, 3);
@@ -484,17 +522,17 @@ __device__ __forceinline__ T u2_grad(const cplx<T> (&p)[NREG], const cplx<T> (&l
 // ---------------------------------------------------------------------------
 template <typename T>
 struct PassArgs {
-  const DevPass *pass;
-  const DevStage *stages;
-  const DevOp *ops;
-  const DevDiag *diags;
-  const DevTerm *terms;
-  const DevPerm *perms;
-  const cplx<T> *mats;
-  const cplx<T> *mats_ps;
+  kptr<DevPass> pass;
+  kptr<DevStage> stages;
+  kptr<DevOp> ops;
+  kptr<DevDiag> diags;
+  kptr<DevTerm> terms;
+  kptr<DevPerm> perms;
+  kptr<cplx<T>> mats;
+  kptr<cplx<T>> mats_ps;
   int mats_ps_stride;
-  const double *dbl;
-  const double *dbl_ps;
+  kptr<double> dbl;
+  kptr<double> dbl_ps;
   int dbl_ps_stride;
   const cplx<T> *src0;
   cplx<T> *dst0;
@@ -509,6 +547,34 @@ struct PassArgs {
 template <typename T>
 __device__ __forceinline__ T seg_reduce(T v, int seg_log) {
   for (int m = 1; m < (1 << seg_log); m <<= 1) v += __shfl_xor(v, m);
+  return v;
+}
+
+// Cross-lane adds with DPP (no LDS traffic).  Steps 1-4 leave the sum of each
+// aligned group of 2, 4, 8, 16 lanes in every lane of the group; step 5 leaves
+// the 32-lane sums in lanes 16-31 and 48-63, step 6 the 64-lane sum in lanes 48-63.
+template <int CTRL, int ROWMASK>
+__device__ __forceinline__ float dpp_add(float v) {
+  const int t = __builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, ROWMASK, 0xF, true);
+  return v + __int_as_float(t);
+}
+template <int CTRL, int ROWMASK>
+__device__ __forceinline__ double dpp_add(double v) {
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_update_dpp(0, (int)(b & 0xffffffffll), CTRL, ROWMASK, 0xF, true);
+  const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), CTRL, ROWMASK, 0xF, true);
+  return v + __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
+}
+
+// Sum over aligned segments of 2^seg_log lanes; valid in the last lane of each segment.
+template <typename T>
+__device__ __forceinline__ T seg_sum_dpp(T v, int seg_log) {
+  if (seg_log >= 1) v = dpp_add<0xB1, 0xF>(v);   // quad_perm [1,0,3,2]
+  if (seg_log >= 2) v = dpp_add<0x4E, 0xF>(v);   // quad_perm [2,3,0,1]
+  if (seg_log >= 3) v = dpp_add<0x141, 0xF>(v);  // row_half_mirror
+  if (seg_log >= 4) v = dpp_add<0x140, 0xF>(v);  // row_mirror
+  if (seg_log >= 5) v = dpp_add<0x142, 0xA>(v);  // row_bcast:15 into rows 1 and 3
+  if (seg_log >= 6) v = dpp_add<0x143, 0xC>(v);  // row_bcast:31 into rows 2 and 3
   return v;
 }
 
@@ -534,8 +600,9 @@ __device__ __forceinline__ int thread_sample(const Ctx<T, K> &c, int batch) {
 
 template <typename T, int K>
 __device__ __forceinline__ void write_acc(const Ctx<T, K> &c, const PassArgs<T> &a, T v, int acc) {
-  v = seg_reduce(v, c.seg_log);
-  if ((c.tid & ((1 << c.seg_log) - 1)) == 0) {
+  v = seg_sum_dpp(v, c.seg_log);
+  const int segm = (1 << c.seg_log) - 1;
+  if ((c.tid & segm) == segm) {
     const int seg = c.tid >> c.seg_log;
     int s, u;
     if (c.multi) {
@@ -551,7 +618,7 @@ __device__ __forceinline__ void write_acc(const Ctx<T, K> &c, const PassArgs<T> 
 }
 
 template <typename T>
-__device__ __forceinline__ const cplx<T> *op_mat(const PassArgs<T> &a, const UOp &op, int s) {
+__device__ __forceinline__ kptr<cplx<T>> op_mat(const PassArgs<T> &a, const UOp &op, int s) {
   return (op.flags & F_PERSAMPLE) ? a.mats_ps + (size_t)s * a.mats_ps_stride + op.mat : a.mats + op.mat;
 }
 
@@ -601,7 +668,7 @@ __device__ __forceinline__ void u1_grad_dispatch(const cplx<T> (&p)[NREG], const
   X(0, 1) X(0, 2) X(0, 3) X(1, 0) X(1, 2) X(1, 3) X(2, 0) X(2, 1) X(2, 3) X(3, 0) X(3, 1) X(3, 2)
 
 template <typename T, bool ADJ>
-__device__ __forceinline__ void u2_dispatch(cplx<T> (&v)[NREG], const cplx<T> *m, int r0, int r1) {
+__device__ __forceinline__ void u2_dispatch(cplx<T> (&v)[NREG], kptr<cplx<T>> m, int r0, int r1) {
   switch (r0 * 4 + r1) {
 #define X(a, b) \
   case a * 4 + b: TQS_CASE_MARK(u##a##b); u2_apply<T, a, b, ADJ>(v, m); TQS_CASE_MARK(eu##a##b); break;
@@ -650,10 +717,10 @@ __device__ __forceinline__ T wht_pick(const T (&w)[NREG], int m) {
 // Build the split phase tables of every diagonal op of the pass in LDS.
 template <typename T, int K>
 __device__ __forceinline__ void build_diag_tables(const Ctx<T, K> &c, const PassArgs<T> &a, cplx<T> *tab) {
-  const DevPass *P = a.pass;
+  kptr<DevPass> P = a.pass;
   const int nd = uni(P->n_diag), db = uni(P->diag_begin);
   for (int di = 0; di < nd; ++di) {
-    const DevDiag *dg = a.diags + db + di;
+    kptr<DevDiag> dg = a.diags + db + di;
     const int h = uni(dg->h), nx = uni(dg->n_extra), off = uni(dg->lds_off);
     const int tbeg = uni(dg->term_begin), tend = uni(dg->term_end);
     const int ex0 = nx > 0 ? uni(dg->extra[0]) : -1, ex1 = nx > 1 ? uni(dg->extra[1]) : -1;
@@ -663,7 +730,7 @@ __device__ __forceinline__ void build_diag_tables(const Ctx<T, K> &c, const Pass
       const int e = low ? idx : idx - nl;
       double ang = 0.0;
       for (int ti = tbeg; ti < tend; ++ti) {
-        const DevTerm *tm = a.terms + ti;
+        kptr<DevTerm> tm = a.terms + ti;
         const int tab_id = uni(tm->tab);
         if (low ? (tab_id != 0) : (tab_id == 0)) continue;
         const int nb = uni(tm->nbits);
@@ -684,8 +751,8 @@ __device__ __forceinline__ void build_diag_tables(const Ctx<T, K> &c, const Pass
           v = (v << 1) | bit;
         }
         const int ang_off = uni(tm->ang);
-        const double *an = uni(tm->per_sample) ? a.dbl_ps + (size_t)c.sample0 * a.dbl_ps_stride + ang_off
-                                               : a.dbl + ang_off;
+        kptr<double> an = uni(tm->per_sample) ? a.dbl_ps + (size_t)c.sample0 * a.dbl_ps_stride + ang_off
+                                              : a.dbl + ang_off;
         ang += an[v];
       }
       double s, co;
@@ -702,7 +769,7 @@ struct DiagView {
   int h, nx, lds_off, th_off, x0, x1, x2;
 };
 
-__device__ __forceinline__ DiagView diag_view(const DevDiag *dg) {
+__device__ __forceinline__ DiagView diag_view(kptr<DevDiag> dg) {
   DiagView v;
   v.h = uni(dg->h);
   v.nx = uni(dg->n_extra);
@@ -728,7 +795,7 @@ __device__ __forceinline__ void run_stage(const Ctx<T, K> &c, const PassArgs<T> 
   const int op0_kind = uni(a.ops[S.op_begin].kind);
   if (op0_kind == OP_PERM) {
     // in-tile permutation: forward new[t] = old[src(t)], backward the inverse
-    const DevPerm *pm = a.perms + uni(a.ops[S.op_begin].aux);
+    kptr<DevPerm> pm = a.perms + uni(a.ops[S.op_begin].aux);
     cplx<T> vp[NREG], vl[NREG];
     int srcs[NREG];
     uint32_t sthr = uniu(pm->cxor);
@@ -795,7 +862,7 @@ __device__ __forceinline__ void run_stage(const Ctx<T, K> &c, const PassArgs<T> 
   for (int oi = 0; oi < nops; ++oi) {
     const UOp op = load_op(a.ops + (BWD ? (S.op_end - 1 - oi) : (S.op_begin + oi)));
     if (op.kind == OP_U1 || op.kind == OP_GRAD1) {
-      const cplx<T> *mg = op_mat(a, op, s_thr);
+      kptr<cplx<T>> mg = op_mat(a, op, s_thr);
       if (BWD && (op.flags & F_GRAD)) {
         T sx = 0, sy = 0, sz = 0;
         u1_grad_dispatch(vp, vl, op.r0, sx, sy, sz);
@@ -805,12 +872,12 @@ __device__ __forceinline__ void run_stage(const Ctx<T, K> &c, const PassArgs<T> 
       }
       if (op.kind == OP_U1) {
         cplx<T> m[4];
-        m[0] = mg[0]; m[1] = mg[1]; m[2] = mg[2]; m[3] = mg[3];
+        m[0] = kld(mg, 0); m[1] = kld(mg, 1); m[2] = kld(mg, 2); m[3] = kld(mg, 3);
         u1_dispatch<T, BWD>(vp, m, op.r0, op.flags);
         if (BWD) u1_dispatch<T, true>(vl, m, op.r0, op.flags);
       }
     } else if (op.kind == OP_U2) {
-      const cplx<T> *mg = op_mat(a, op, s_thr);
+      kptr<cplx<T>> mg = op_mat(a, op, s_thr);
       if (BWD && (op.flags & F_GRAD)) {
         const T g = u2_grad_dispatch(vp, vl, op.r0, op.r1, op.aux);
         write_acc(c, a, g, op.acc);
@@ -818,7 +885,7 @@ __device__ __forceinline__ void run_stage(const Ctx<T, K> &c, const PassArgs<T> 
       u2_dispatch<T, BWD>(vp, mg, op.r0, op.r1);
       if (BWD) u2_dispatch<T, true>(vl, mg, op.r0, op.r1);
     } else if (op.kind == OP_DIAG) {
-      const DevDiag *dg = a.diags + uni(a.pass->diag_begin) + op.aux;
+      kptr<DevDiag> dg = a.diags + uni(a.pass->diag_begin) + op.aux;
       const DiagView dv = diag_view(dg);
       if (BWD && (op.flags & F_GRAD)) {
         // w = Im(conj(l) p); parity sums over each term's bits via a register WHT
@@ -828,7 +895,7 @@ __device__ __forceinline__ void run_stage(const Ctx<T, K> &c, const PassArgs<T> 
         wht16(w);
         const int tbeg = uni(dg->term_begin), tend = uni(dg->term_end);
         for (int ti = tbeg; ti < tend; ++ti) {
-          const DevTerm *tm = a.terms + ti;
+          kptr<DevTerm> tm = a.terms + ti;
           const int tacc = uni(tm->acc);
           if (tacc < 0) continue;
           int m = 0;
@@ -880,7 +947,7 @@ __global__ void __launch_bounds__(1 << (K - RB)) k_pass(PassArgs<T> a) {
   cplx<T> *Lp = reinterpret_cast<cplx<T> *>(smem);
   cplx<T> *Ll = Lp + NE;
   cplx<T> *tab = Lp + (BWD ? 2 : 1) * NE;
-  const DevPass *P = a.pass;
+  kptr<DevPass> P = a.pass;
 
   Ctx<T, K> c;
   c.tid = threadIdx.x;
@@ -921,11 +988,11 @@ __global__ void __launch_bounds__(1 << (K - RB)) k_pass(PassArgs<T> a) {
   // map used for this direction's load and store
   const int lmap = uni(BWD ? P->has_store_map : P->has_load_map);
   const int smap = uni(BWD ? P->has_load_map : P->has_store_map);
-  const uint32_t *ltc = BWD ? P->store_tcol : P->load_tcol;
-  const uint32_t *lrc = BWD ? P->store_rcol : P->load_rcol;
+  kptr<uint32_t> ltc = BWD ? P->store_tcol : P->load_tcol;
+  kptr<uint32_t> lrc = BWD ? P->store_rcol : P->load_rcol;
   const uint32_t lc = uniu(BWD ? P->store_c : P->load_c);
-  const uint32_t *stc = BWD ? P->load_tcol : P->store_tcol;
-  const uint32_t *src_ = BWD ? P->load_rcol : P->store_rcol;
+  kptr<uint32_t> stc = BWD ? P->load_tcol : P->store_tcol;
+  kptr<uint32_t> src_ = BWD ? P->load_rcol : P->store_rcol;
   const uint32_t sc = uniu(BWD ? P->load_c : P->store_c);
   uint32_t lbase = lc, lthr = 0, sbase = sc, sthr = 0;
   if (!c.multi) {
@@ -959,27 +1026,27 @@ __global__ void __launch_bounds__(1 << (K - RB)) k_pass(PassArgs<T> a) {
   if (fwd_embed) {
     // product state: amplitude = prod over wires of the wire's state component
     if (!c.multi) {
-      const cplx<T> *em = embed_ps ? a.mats_ps + (size_t)c.sample0 * a.mats_ps_stride + embed_mat
-                                   : a.mats + embed_mat;
+      kptr<cplx<T>> em = embed_ps ? a.mats_ps + (size_t)c.sample0 * a.mats_ps_stride + embed_mat
+                                  : a.mats + embed_mat;
       // base (rest) bits and thread bits
       cplx<T> cth = cmk<T>(1, 0);
       for (int r = 0; r < c.nv - K; ++r) {
         const int p = uni(P->rest[r]);
-        const cplx<T> *m = em + 4 * (n - 1 - p);
-        cth = cmul(cth, ((c.base >> p) & 1) ? m[2] : m[0]);
+        kptr<cplx<T>> m = em + 4 * (n - 1 - p);
+        cth = cmul(cth, kld(m, ((c.base >> p) & 1) ? 2 : 0));
       }
       for (int b = 0; b < K - RB; ++b) {
         const int p = uni(P->tpos[b]);
-        const cplx<T> *m = em + 4 * (n - 1 - p);
-        cth = cmul(cth, ((c.tid >> b) & 1) ? m[2] : m[0]);
+        kptr<cplx<T>> m = em + 4 * (n - 1 - p);
+        cth = cmul(cth, kld(m, ((c.tid >> b) & 1) ? 2 : 0));
       }
       cplx<T> f[RB][2];
 #pragma unroll
       for (int b = 0; b < RB; ++b) {
         const int p = uni(P->tpos[K - RB + b]);
-        const cplx<T> *m = em + 4 * (n - 1 - p);
-        f[b][0] = m[0];
-        f[b][1] = m[2];
+        kptr<cplx<T>> m = em + 4 * (n - 1 - p);
+        f[b][0] = kld(m, 0);
+        f[b][1] = kld(m, 2);
       }
 #pragma unroll
       for (int i = 0; i < NREG; ++i) {
@@ -996,12 +1063,12 @@ __global__ void __launch_bounds__(1 << (K - RB)) k_pass(PassArgs<T> a) {
         const int j = t & ((1 << c.nv) - 1);
         cplx<T> v = cmk<T>(0, 0);
         if (s < a.batch && j < (1 << n)) {
-          const cplx<T> *em = embed_ps ? a.mats_ps + (size_t)s * a.mats_ps_stride + embed_mat
-                                       : a.mats + embed_mat;
+          kptr<cplx<T>> em = embed_ps ? a.mats_ps + (size_t)s * a.mats_ps_stride + embed_mat
+                                      : a.mats + embed_mat;
           v = cmk<T>(1, 0);
           for (int p = 0; p < n; ++p) {
-            const cplx<T> *m = em + 4 * (n - 1 - p);
-            v = cmul(v, ((j >> p) & 1) ? m[2] : m[0]);
+            kptr<cplx<T>> m = em + 4 * (n - 1 - p);
+            v = cmul(v, kld(m, ((j >> p) & 1) ? 2 : 0));
           }
         }
         Lp[swz<T>(t)] = v;
@@ -1151,11 +1218,16 @@ __device__ __forceinline__ bool rd_elem(const RdCtx &c, int n, int batch, int t,
 }
 
 // Per sample and tile: total probability and the signed sum over each tile bit.
-template <typename T>
+// COAL: a sample spans whole tiles; element i*NTE + tid (lane-contiguous loads),
+// register bits are tile bits KE-4..KE-1.  Otherwise thread tid holds
+// elements 16*tid .. 16*tid+15 (register bits 0..3) so that no thread mixes
+// samples.
+template <typename T, bool COAL>
 __global__ void __launch_bounds__(NTE) k_expval(ReadArgs<T> a) {
   const int n = a.n;
   const int tid = threadIdx.x;
   const RdCtx c = rd_ctx(n);
+  constexpr int RB0 = COAL ? KE - RB : 0;      // first register tile bit
   double tot = 0.0;
   double sr[RB];
 #pragma unroll
@@ -1164,7 +1236,8 @@ __global__ void __launch_bounds__(NTE) k_expval(ReadArgs<T> a) {
   for (int i = 0; i < NREG; ++i) {
     long long g;
     double p = 0.0;
-    if (rd_elem(c, n, a.batch, tid * NREG + i, g)) {
+    const int t = COAL ? tid + i * NTE : tid * NREG + i;
+    if (rd_elem(c, n, a.batch, t, g)) {
       const cplx<T> v = a.psi[g];
       p = (double)v.x * (double)v.x + (double)v.y * (double)v.y;
     }
@@ -1172,24 +1245,29 @@ __global__ void __launch_bounds__(NTE) k_expval(ReadArgs<T> a) {
 #pragma unroll
     for (int b = 0; b < RB; ++b) sr[b] += ((i >> b) & 1) ? -p : p;
   }
-  // values: 0 = total, 1 + b = signed sum over tile bit b (b < 4 from
-  // registers, b >= 4 from thread bit b - 4)
+  // values: 0 = total, 1 + b = signed sum over tile bit b
   double vals[KE + 1];
   vals[0] = tot;
 #pragma unroll
-  for (int b = 0; b < RB; ++b) vals[1 + b] = sr[b];
-#pragma unroll
-  for (int b = RB; b < KE; ++b) vals[1 + b] = ((tid >> (b - RB)) & 1) ? -tot : tot;
+  for (int b = 0; b < KE; ++b) {
+    if (b >= RB0 && b < RB0 + RB)
+      vals[1 + b] = sr[b - RB0];
+    else {
+      const int tb = COAL ? b : b - RB;        // thread-index bit of tile bit b
+      vals[1 + b] = ((tid >> tb) & 1) ? -tot : tot;
+    }
+  }
   const int seg_log = c.tps_log < 6 ? c.tps_log : 6;
 #pragma unroll
-  for (int v = 0; v <= KE; ++v) vals[v] = seg_reduce(vals[v], seg_log);
+  for (int v = 0; v <= KE; ++v) vals[v] = seg_sum_dpp(vals[v], seg_log);
+  const int segm = (1 << seg_log) - 1;
   const long long units = c.multi ? 1 : (1ll << (c.nv - KE));
   const long long u = c.multi ? 0 : ((long long)blockIdx.x & (units - 1));
   if (c.tps_log >= 6) {
     // a sample spans whole waves: combine its waves through LDS
     __shared__ double red[(NTE / 64) * (KE + 1)];
     const int wave = tid >> 6;
-    if ((tid & 63) == 0)
+    if ((tid & 63) == 63)
       for (int v = 0; v <= KE; ++v) red[wave * (KE + 1) + v] = vals[v];
     __syncthreads();
     const int wps = 1 << (c.tps_log - 6);          // waves per sample
@@ -1201,7 +1279,7 @@ __global__ void __launch_bounds__(NTE) k_expval(ReadArgs<T> a) {
       const long long smp = c.sample0 + sl;
       if (smp < a.batch) a.partials[(smp * units + u) * (KE + 1) + v] = s;
     }
-  } else if ((tid & ((1 << seg_log) - 1)) == 0) {
+  } else if ((tid & segm) == segm) {
     const long long smp = c.sample0 + (tid >> seg_log);
     if (smp < a.batch)
       for (int v = 0; v <= KE; ++v) a.partials[(smp * units + u) * (KE + 1) + v] = vals[v];
@@ -1232,31 +1310,34 @@ __global__ void k_expval_final(const double *partials, double *expz, double *nor
 }
 
 // lambda = psi * h with h(j) = sum_i g_i (1 - 2 b_i(j)), per sample
-template <typename T>
+template <typename T, bool COAL>
 __global__ void __launch_bounds__(NTE) k_adj_init(ReadArgs<T> a) {
   const int n = a.n;
   const int tid = threadIdx.x;
   const RdCtx c = rd_ctx(n);
-  // thread part: state bits >= 4 of the thread's elements
+  constexpr int RB0 = COAL ? KE - RB : 0;
   long long g0;
-  const bool any = rd_elem(c, n, a.batch, tid * NREG, g0);
-  if (!any && c.multi) {
-    // the thread's first element is padding or past the batch; so are the rest
-    return;
-  }
+  if (!rd_elem(c, n, a.batch, COAL ? tid : tid * NREG, g0)) return;   // padding / past the batch
   const long long s = g0 >> n;
   const double *gg = a.g + s * n;
   const uint32_t j0 = (uint32_t)(g0 & ((1ll << n) - 1));
+  // thread part: every state bit except the register bits
   double hthr = 0.0;
-  for (int p = RB; p < n; ++p) hthr += ((j0 >> p) & 1) ? -gg[n - 1 - p] : gg[n - 1 - p];
+  for (int p = 0; p < n; ++p) {
+    if (p >= RB0 && p < RB0 + RB) continue;
+    hthr += ((j0 >> p) & 1) ? -gg[n - 1 - p] : gg[n - 1 - p];
+  }
 #pragma unroll
   for (int i = 0; i < NREG; ++i) {
     long long g;
-    if (!rd_elem(c, n, a.batch, tid * NREG + i, g)) continue;
+    const int t = COAL ? tid + i * NTE : tid * NREG + i;
+    if (!rd_elem(c, n, a.batch, t, g)) continue;
     double h = hthr;
 #pragma unroll
-    for (int p = 0; p < RB; ++p)
-      if (p < n) h += ((i >> p) & 1) ? -gg[n - 1 - p] : gg[n - 1 - p];
+    for (int b = 0; b < RB; ++b) {
+      const int p = RB0 + b;
+      if (p < n) h += ((i >> b) & 1) ? -gg[n - 1 - p] : gg[n - 1 - p];
+    }
     const cplx<T> v = a.psi[g];
     a.lam[g] = cmk<T>((T)(v.x * h), (T)(v.y * h));
   }

@@ -32,8 +32,27 @@ static tqs_status from_msg(const std::string &m) {
       return fail(TQS_EDEVICE, std::string(#expr) + ": " + hipGetErrorString(e_));         \
   } while (0)
 
+// Optional per-launch timing with HIP events (option "profile"): every kernel
+// launch is bracketed by two events on its stream; tqs_profile_report waits for
+// them and aggregates duration and algorithmic bytes / flops per kernel kind.
+struct ProfRec {
+  int kind;
+  double bytes, flops;
+  hipEvent_t e0, e1;
+};
+struct ProfAgg {
+  long long count = 0;
+  double ms = 0, bytes = 0, flops = 0;
+};
+
 struct tqs_circuit {
   Plan plan;
+  bool profile = false;
+  std::mutex pmu;
+  std::vector<ProfRec> pending;
+  std::vector<hipEvent_t> pool;
+  std::vector<std::string> kind_names;
+  std::vector<ProfAgg> agg;
   std::vector<LayerSpec> layers;
   int n = 0, dtype = 0, mode = 0, tile_bits = 0;
   std::mutex mu;
@@ -167,6 +186,65 @@ int pass_grid(const DevPass &d, int B) {
   return (B + spw - 1) / spw;
 }
 
+int prof_kind(tqs_circuit *c, const std::string &name) {
+  for (size_t i = 0; i < c->kind_names.size(); ++i)
+    if (c->kind_names[i] == name) return (int)i;
+  c->kind_names.push_back(name);
+  c->agg.emplace_back();
+  return (int)c->kind_names.size() - 1;
+}
+
+hipEvent_t prof_event(tqs_circuit *c) {
+  if (!c->pool.empty()) {
+    hipEvent_t e = c->pool.back();
+    c->pool.pop_back();
+    return e;
+  }
+  hipEvent_t e = nullptr;
+  if (hipEventCreate(&e) != hipSuccess) return nullptr;
+  return e;
+}
+
+// Brackets one launch; call begin() before and end() after the launch.
+struct ProfScope {
+  tqs_circuit *c;
+  hipStream_t s;
+  ProfRec r;
+  bool on;
+  ProfScope(tqs_circuit *c_, hipStream_t s_, const std::string &name, double bytes, double flops)
+      : c(c_), s(s_), on(c_->profile) {
+    if (!on) return;
+    std::lock_guard<std::mutex> lk(c->pmu);
+    r.kind = prof_kind(c, name);
+    r.bytes = bytes;
+    r.flops = flops;
+    r.e0 = prof_event(c);
+    r.e1 = prof_event(c);
+    if (!r.e0 || !r.e1) {
+      on = false;
+      return;
+    }
+    (void)hipEventRecord(r.e0, s);
+  }
+  void end() {
+    if (!on) return;
+    (void)hipEventRecord(r.e1, s);
+    std::lock_guard<std::mutex> lk(c->pmu);
+    c->pending.push_back(r);
+    on = false;
+  }
+};
+
+// Algorithmic flops of one op application on one amplitude (forward).
+double op_flops(const DevOp &o) {
+  switch (o.kind) {
+    case OP_U1: return (o.flags & F_DIAGONAL) ? 6.0 : ((o.flags & F_REAL) ? 8.0 : 16.0);
+    case OP_U2: return 32.0;
+    case OP_DIAG: return 12.0;
+    default: return 0.0;
+  }
+}
+
 template <typename T, int K, bool BWD>
 void launch_pass_k(const PassArgs<T> &a, int grid, size_t lds, hipStream_t s) {
   hipLaunchKernelGGL((k_pass<T, K, BWD>), dim3(grid), dim3(1 << (K - RB)), lds, s, a);
@@ -179,17 +257,17 @@ tqs_status launch_pass(tqs_circuit *c, int pi, int B, const cplx<T> *src0, cplx<
   const Plan &P = c->plan;
   const DevPass &d = P.dpass[pi];
   PassArgs<T> a;
-  a.pass = c->d_pass + pi;
-  a.stages = c->d_stage;
-  a.ops = c->d_op;
-  a.diags = c->d_diag;
-  a.terms = c->d_term;
-  a.perms = c->d_perm;
-  a.mats = reinterpret_cast<const cplx<T> *>(ws + L.mats);
-  a.mats_ps = reinterpret_cast<const cplx<T> *>(ws + L.mats_ps);
+  a.pass = kc(c->d_pass + pi);
+  a.stages = kc(c->d_stage);
+  a.ops = kc(c->d_op);
+  a.diags = kc(c->d_diag);
+  a.terms = kc(c->d_term);
+  a.perms = kc(c->d_perm);
+  a.mats = kc(reinterpret_cast<const cplx<T> *>(ws + L.mats));
+  a.mats_ps = kc(reinterpret_cast<const cplx<T> *>(ws + L.mats_ps));
   a.mats_ps_stride = P.n_mats_ps;
-  a.dbl = reinterpret_cast<const double *>(ws + L.dbl);
-  a.dbl_ps = reinterpret_cast<const double *>(ws + L.dbl_ps);
+  a.dbl = kc(reinterpret_cast<const double *>(ws + L.dbl));
+  a.dbl_ps = kc(reinterpret_cast<const double *>(ws + L.dbl_ps));
   a.dbl_ps_stride = P.n_dbl_ps;
   a.src0 = src0;
   a.dst0 = dst0;
@@ -202,12 +280,28 @@ tqs_status launch_pass(tqs_circuit *c, int pi, int B, const cplx<T> *src0, cplx<
   const int grid = pass_grid(d, B);
   const size_t es = sizeof(cplx<T>);
   const size_t lds = ((size_t)(BWD ? 2 : 1) * ((size_t)1 << d.K) + (size_t)d.diag_lds) * es;
+  double bytes = 0, flops = 0;
+  if (c->profile) {
+    const double amps = (double)B * (double)(1ll << P.n);
+    if (BWD)
+      bytes = amps * es * (2.0 + (d.skip_bwd_store ? 0.0 : 2.0));
+    else
+      bytes = amps * es * ((d.load_mode == LOAD_GLOBAL ? 1.0 : 0.0) + 1.0);
+    double f = 0;
+    for (int st = d.stage_begin; st < d.stage_begin + d.n_stages; ++st)
+      for (int oi = P.dstage[st].op_begin; oi < P.dstage[st].op_end; ++oi) f += op_flops(P.dop[oi]);
+    // backward: both states are uncomputed, plus the gradient sums (~1x)
+    flops = amps * f * (BWD ? 3.0 : 1.0);
+  }
+  ProfScope ps(c, s, std::string(BWD ? "pass_bwd_K" : "pass_fwd_K") + std::to_string(d.K) +
+                         (sizeof(T) == 8 ? "_c128" : "_c64"), bytes, flops);
   switch (d.K) {
     case 10: launch_pass_k<T, 10, BWD>(a, grid, lds, s); break;
     case 11: launch_pass_k<T, 11, BWD>(a, grid, lds, s); break;
     case 12: launch_pass_k<T, 12, BWD>(a, grid, lds, s); break;
     default: return fail(TQS_EUNSUPPORTED, "tile size not built");
   }
+  ps.end();
   HIP_TRY(hipGetLastError());
   return TQS_OK;
 }
@@ -218,8 +312,8 @@ tqs_status do_prep(tqs_circuit *c, int B, const double *w, const double *x, char
   const Plan &P = c->plan;
   if (P.prep.empty()) return TQS_OK;
   PrepArgs<T> a;
-  a.items = c->d_prep;
-  a.factors = c->d_fac;
+  a.items = kc(c->d_prep);
+  a.factors = kc(c->d_fac);
   a.n_items = (int)P.prep.size();
   a.w = w;
   a.x = x;
@@ -232,7 +326,9 @@ tqs_status do_prep(tqs_circuit *c, int B, const double *w, const double *x, char
   a.dbl_ps = reinterpret_cast<double *>(ws + L.dbl_ps);
   a.dbl_ps_stride = P.n_dbl_ps;
   dim3 grid((B + 63) / 64, (unsigned)P.prep.size());
+  ProfScope ps(c, s, "prep", 0.0, 0.0);
   hipLaunchKernelGGL((k_prep<T>), grid, dim3(64), 0, s, a);
+  ps.end();
   HIP_TRY(hipGetLastError());
   return TQS_OK;
 }
@@ -277,7 +373,13 @@ tqs_status expval_t(const tqs_circuit *c, int B, const void *state, double *expz
   a.batch = B;
   const long long padded = (long long)B << P.nv;
   const long long blocks = (padded + (1ll << KE) - 1) >> KE;
-  hipLaunchKernelGGL((k_expval<T>), dim3((unsigned)blocks), dim3(NTE), 0, s, a);
+  ProfScope ps(const_cast<tqs_circuit *>(c), s, "expval", (double)B * (double)(1ll << P.n) * sizeof(cplx<T>),
+               (double)B * (double)(1ll << P.n) * 8.0);
+  if (P.nv >= KE)
+    hipLaunchKernelGGL((k_expval<T, true>), dim3((unsigned)blocks), dim3(NTE), 0, s, a);
+  else
+    hipLaunchKernelGGL((k_expval<T, false>), dim3((unsigned)blocks), dim3(NTE), 0, s, a);
+  ps.end();
   HIP_TRY(hipGetLastError());
   const int tot = B * (P.n + 1);
   hipLaunchKernelGGL(k_expval_final, dim3((tot + 255) / 256), dim3(256), 0, s,
@@ -306,7 +408,13 @@ tqs_status adjoint_t(tqs_circuit *c, int B, const double *w, const double *x, vo
     a.batch = B;
     const long long padded = (long long)B << P.nv;
     const long long blocks = (padded + (1ll << KE) - 1) >> KE;
-    hipLaunchKernelGGL((k_adj_init<T>), dim3((unsigned)blocks), dim3(NTE), 0, s, a);
+    ProfScope ps(c, s, "adj_init", 2.0 * (double)B * (double)(1ll << P.n) * sizeof(cplx<T>),
+                 (double)B * (double)(1ll << P.n) * 4.0);
+    if (P.nv >= KE)
+      hipLaunchKernelGGL((k_adj_init<T, true>), dim3((unsigned)blocks), dim3(NTE), 0, s, a);
+    else
+      hipLaunchKernelGGL((k_adj_init<T, false>), dim3((unsigned)blocks), dim3(NTE), 0, s, a);
+    ps.end();
     HIP_TRY(hipGetLastError());
   }
   cplx<T> *pc = S, *lc = LA;
@@ -324,6 +432,7 @@ tqs_status adjoint_t(tqs_circuit *c, int B, const double *w, const double *x, vo
     lc = ld;
   }
   double *A = reinterpret_cast<double *>(ws + L.A);
+  ProfScope psf(c, s, "grad_finalize", 0.0, 0.0);
   if (P.n_acc > 0) {
     const long long tot = (long long)P.n_acc * B;
     hipLaunchKernelGGL((k_acc_reduce<T>), dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s,
@@ -339,6 +448,7 @@ tqs_status adjoint_t(tqs_circuit *c, int B, const double *w, const double *x, vo
                        P.n_weights, gx ? P.n_features : 0, B, gw, gx);
     HIP_TRY(hipGetLastError());
   }
+  psf.end();
   return TQS_OK;
 }
 
@@ -397,6 +507,12 @@ tqs_status tqs_circuit_create(int32_t n_qubits, const tqs_layer *layers, int32_t
 
 tqs_status tqs_circuit_destroy(tqs_circuit *c) {
   if (!c) return TQS_OK;
+  for (auto &r : c->pending) {
+    (void)hipEventSynchronize(r.e1);
+    c->pool.push_back(r.e0);
+    c->pool.push_back(r.e1);
+  }
+  for (hipEvent_t e : c->pool) (void)hipEventDestroy(e);
   if (c->dmem) {
     int cur = -1;
     (void)hipGetDevice(&cur);
@@ -478,7 +594,12 @@ tqs_status tqs_adjoint_grad(tqs_circuit *c, int32_t batch, const double *weights
 tqs_status tqs_set_option(tqs_circuit *c, const char *key, int64_t value) {
   if (!c || !key) return fail(TQS_EINVAL, "circuit or key is NULL");
   std::lock_guard<std::mutex> lk(c->mu);
-  if (c->uploaded) return fail(TQS_EINVAL, "options must be set before the first forward call");
+  if (std::strcmp(key, "profile") != 0 && c->uploaded)
+    return fail(TQS_EINVAL, "options must be set before the first forward call");
+  if (std::strcmp(key, "profile") == 0) {
+    c->profile = value != 0;
+    return TQS_OK;
+  }
   if (std::strcmp(key, "mode") == 0) {
     if (value < 0 || value > 3) return fail(TQS_EINVAL, "mode must be 0..3");
     c->mode = (int)value;
@@ -496,6 +617,38 @@ tqs_status tqs_plan_describe(const tqs_circuit *c, char *buf, size_t len) {
   const std::string s = describe_plan(c->plan);
   if (s.size() + 1 > len) return fail(TQS_ENOMEM, "buffer too small");
   std::memcpy(buf, s.c_str(), s.size() + 1);
+  return TQS_OK;
+}
+
+tqs_status tqs_profile_report(tqs_circuit *c, int32_t reset, char *buf, size_t len) {
+  if (!c || !buf || len == 0) return fail(TQS_EINVAL, "bad arguments");
+  std::lock_guard<std::mutex> lk(c->pmu);
+  for (auto &r : c->pending) {
+    HIP_TRY(hipEventSynchronize(r.e1));
+    float ms = 0.f;
+    HIP_TRY(hipEventElapsedTime(&ms, r.e0, r.e1));
+    ProfAgg &a = c->agg[r.kind];
+    a.count += 1;
+    a.ms += ms;
+    a.bytes += r.bytes;
+    a.flops += r.flops;
+    c->pool.push_back(r.e0);
+    c->pool.push_back(r.e1);
+  }
+  c->pending.clear();
+  std::string out = "{";
+  for (size_t i = 0; i < c->agg.size(); ++i) {
+    char tmp[256];
+    snprintf(tmp, sizeof tmp, "%s\"%s\":{\"count\":%lld,\"ms\":%.6f,\"bytes\":%.0f,\"flops\":%.0f}",
+             i ? "," : "", c->kind_names[i].c_str(), c->agg[i].count, c->agg[i].ms, c->agg[i].bytes,
+             c->agg[i].flops);
+    out += tmp;
+  }
+  out += "}";
+  if (reset)
+    for (auto &a : c->agg) a = ProfAgg();
+  if (out.size() + 1 > len) return fail(TQS_ENOMEM, "buffer too small");
+  std::memcpy(buf, out.c_str(), out.size() + 1);
   return TQS_OK;
 }
 

@@ -59,11 +59,13 @@ def lib():
     L.tqs_adjoint_grad.argtypes = [vp, i32, vp, vp, vp, vp, vp, vp, vp, sz, vp]
     L.tqs_set_option.argtypes = [vp, ctypes.c_char_p, i64]
     L.tqs_plan_describe.argtypes = [vp, ctypes.c_char_p, sz]
+    L.tqs_profile_report.argtypes = [vp, i32, ctypes.c_char_p, sz]
     L.tqs_status_string.argtypes = [i32]
     L.tqs_status_string.restype = ctypes.c_char_p
     L.tqs_last_error.restype = ctypes.c_char_p
     for f in ("tqs_circuit_create", "tqs_circuit_destroy", "tqs_circuit_info", "tqs_workspace_size",
-              "tqs_forward", "tqs_expval_z", "tqs_adjoint_grad", "tqs_set_option", "tqs_plan_describe"):
+              "tqs_forward", "tqs_expval_z", "tqs_adjoint_grad", "tqs_set_option", "tqs_plan_describe",
+              "tqs_profile_report"):
         getattr(L, f).restype = i32
     _lib = L
     return L
@@ -142,6 +144,15 @@ class Circuit:
     def plan(self):
         buf = ctypes.create_string_buffer(1 << 20)
         _check(lib().tqs_plan_describe(self._h, buf, len(buf)))
+        return json.loads(buf.value.decode())
+
+    def set_profile(self, on=True):
+        _check(lib().tqs_set_option(self._h, b"profile", int(bool(on))))
+
+    def profile_report(self, reset=True):
+        """Per kernel kind: {count, ms, bytes, flops} of the launches timed so far."""
+        buf = ctypes.create_string_buffer(1 << 16)
+        _check(lib().tqs_profile_report(self._h, int(bool(reset)), buf, len(buf)))
         return json.loads(buf.value.decode())
 
     def workspace_size(self, batch, with_grad=True):
