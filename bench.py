@@ -34,6 +34,10 @@ def parse():
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--no-20q", action="store_true")
     p.add_argument("--mode", default="auto", choices=["auto", "per_layer", "fused"])
+    p.add_argument("--no-serve", action="store_true")
+    p.add_argument("--serve-requests", type=int, default=160)
+    p.add_argument("--serve-max-qubits", type=int, default=16)
+    p.add_argument("--serve-qps-fracs", default="0.5,0.8,0.95")
     return p.parse_args()
 
 
@@ -115,6 +119,60 @@ def time_jobs(jobs, steps, warmup):
     return ms, wall / steps * 1e3, merged
 
 
+def serving_bench(n_req, n_max, fracs, seed=0, streams=4, budget=160 << 30):
+    """Continuous batching vs the plain per-request path on one Poisson trace of
+    rotation + CNOT-ring circuits (qubits U{6..n_max}, batch log-U[1, 512],
+    blocks U{2..20}, 30% forward+gradient)."""
+    import numpy as np
+    import workloads as W
+    from paper_2506_04891_amd.serve import GpuExecutor, Request, Server
+
+    def make(qps):
+        trace = W.serving_trace(n_req, qps=qps, seed=seed, n_range=(6, n_max))
+        reqs = []
+        for t in trace:
+            layers, w, x = W.request_params(t, seed=seed)
+            reqs.append((t.t_arrive, Request(t.n, layers, w, x, want_grad=t.want_grad, rid=t.rid)))
+        return reqs
+
+    def run(reqs, plain, ex):
+        srv = Server(ex, budget_bytes=budget, streams=streams, plain=plain)
+        t0 = time.perf_counter()
+        futs = []
+        for ta, r in reqs:
+            dt = t0 + ta - time.perf_counter()
+            if dt > 0:
+                time.sleep(dt)
+            futs.append(srv.submit(r))
+        for f in futs:
+            f.result(timeout=600)
+        st = srv.stats()
+        srv.close()
+        return st
+
+    ex = GpuExecutor(streams=streams, graphs=True)
+    ex_plain = GpuExecutor(streams=1, graphs=False)
+    # warm-up: compile every circuit and capture graphs (untimed)
+    base = make(1e6)
+    run([(0.0, Request(r.n, r.layers, r.weights, r.features, r.want_grad)) for _, r in base], False, ex)
+    run([(0.0, Request(r.n, r.layers, r.weights, r.features, r.want_grad)) for _, r in base], True, ex_plain)
+    sat = run([(0.0, r) for _, r in make(1e6)], False, ex)
+    req_per_s = sat["requests"] / max(1e-9, (sat["evals"] / max(sat["evals_per_s"], 1e-9)))
+    out = {"trace": f"{n_req} requests, qubits U{{6..{n_max}}}, batch log-U[1,512], blocks U{{2..20}}, "
+                    f"30% forward+gradient, seed {seed}; {streams} streams; warm circuits and graphs",
+           "saturation": {"requests_per_s": round(req_per_s, 1), "evals_per_s": round(sat["evals_per_s"], 1)},
+           "points": []}
+    for frac in fracs:
+        qps = frac * req_per_s
+        cb = run(make(qps), False, ex)
+        pl = run(make(qps), True, ex_plain)
+        out["points"].append({"qps": round(qps, 1), "frac_of_saturation": frac,
+                              "continuous": {k: round(cb[k], 3) for k in ("p50_ms", "p99_ms", "evals_per_s")}
+                              | {"launches": cb["launches"]},
+                              "plain": {k: round(pl[k], 3) for k in ("p50_ms", "p99_ms", "evals_per_s")}})
+    return out
+
+
 def cpu_baseline(sample=2):
     """The oracle (numpy complex128, per-gate contraction) on `sample` samples
     of each 16-qubit circuit: forward <Z_i> and adjoint gradients."""
@@ -183,6 +241,9 @@ def main():
                       "roofline": roofline(rep20),
                       "kernels": {k: {"count": v["count"], "ms": round(v["ms"], 3)} for k, v in rep20.items()}}
         del j20
+    if not a.no_serve:
+        out["serving"] = serving_bench(a.serve_requests, a.serve_max_qubits,
+                                       [float(f) for f in a.serve_qps_fracs.split(",")])
     out["cpu_baseline"] = None if a.no_cpu_baseline else cpu_baseline()
     print(json.dumps(out))
 

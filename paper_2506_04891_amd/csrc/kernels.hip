@@ -98,7 +98,7 @@ __device__ __forceinline__ uint32_t uniu(uint32_t x) {
 }
 
 struct UOp {
-  int kind, flags, r0, r1, mat, acc, aux;
+  int kind, flags, r0, r1, mat, acc, aux, sub;
 };
 __device__ __forceinline__ UOp load_op(kptr<DevOp> p) {
   UOp o;
@@ -109,6 +109,7 @@ __device__ __forceinline__ UOp load_op(kptr<DevOp> p) {
   o.mat = uni(p->mat);
   o.acc = uni(p->acc);
   o.aux = uni(p->aux);
+  o.sub = uni(p->sub);
   return o;
 }
 struct UStage {
@@ -487,6 +488,67 @@ __device__ __forceinline__ void u2_apply(cplx<T> (&v)[NREG], kptr<cplx<T>> mg) {
   }
 }
 
+// Structured 4x4 ops on the quads of register bits (R0 = more significant).
+template <typename T, int R0, int R1, bool ADJ, int KIND>
+__device__ __forceinline__ void u2s_apply(cplx<T> (&v)[NREG], kptr<cplx<T>> mg) {
+  T c = 0, sn = 0;
+  if (KIND == U2_MS) {
+    c = mg[0].x;             // cos(pi t)
+    sn = -mg[3].y;           // entry (0,3) = -i sin(pi t)
+    if (ADJ) sn = -sn;
+  }
+  cplx<T> d0, d1, d2, d3;
+  if (KIND == U2_DIAG) {
+    d0 = kld(mg, 0); d1 = kld(mg, 5); d2 = kld(mg, 10); d3 = kld(mg, 15);
+    if (ADJ) { d0 = cconj(d0); d1 = cconj(d1); d2 = cconj(d2); d3 = cconj(d3); }
+  }
+  const T r = (T)0.70710678118654752440;
+#pragma unroll
+  for (int j = 0; j < NREG; ++j) {
+    if (j & ((1 << R0) | (1 << R1))) continue;
+    const int i0 = j, i1 = j | (1 << R1), i2 = j | (1 << R0), i3 = j | (1 << R0) | (1 << R1);
+    const cplx<T> a0 = v[i0], a1 = v[i1], a2 = v[i2], a3 = v[i3];
+    if (KIND == U2_CNOT) {
+      v[i2] = a3; v[i3] = a2;
+    } else if (KIND == U2_SWAP) {
+      v[i1] = a2; v[i2] = a1;
+    } else if (KIND == U2_CZ) {
+      v[i3] = cmk(-a3.x, -a3.y);
+    } else if (KIND == U2_MS) {
+      // out_k = c a_k - i s a_{k^3}
+      v[i0] = cmk(c * a0.x + sn * a3.y, c * a0.y - sn * a3.x);
+      v[i3] = cmk(c * a3.x + sn * a0.y, c * a3.y - sn * a0.x);
+      v[i1] = cmk(c * a1.x + sn * a2.y, c * a1.y - sn * a2.x);
+      v[i2] = cmk(c * a2.x + sn * a1.y, c * a2.y - sn * a1.x);
+    } else if (KIND == U2_ECR) {
+      // self-inverse: rows [0,1,0,i], [1,0,-i,0], [0,i,0,1], [-i,0,1,0] / sqrt(2)
+      v[i0] = cmk((a1.x - a3.y) * r, (a1.y + a3.x) * r);
+      v[i1] = cmk((a0.x + a2.y) * r, (a0.y - a2.x) * r);
+      v[i2] = cmk((a3.x - a1.y) * r, (a3.y + a1.x) * r);
+      v[i3] = cmk((a2.x + a0.y) * r, (a2.y - a0.x) * r);
+    } else if (KIND == U2_DIAG) {
+      v[i0] = cmul(a0, d0); v[i1] = cmul(a1, d1); v[i2] = cmul(a2, d2); v[i3] = cmul(a3, d3);
+    }
+  }
+}
+
+// Im<l| P(x)P |p> for P = X (code 1|1<<2) or Z (code 3|3<<2) on both bits.
+template <typename T, int R0, int R1, bool XX>
+__device__ __forceinline__ T u2s_grad(const cplx<T> (&p)[NREG], const cplx<T> (&l)[NREG]) {
+  T acc = 0;
+#pragma unroll
+  for (int j = 0; j < NREG; ++j) {
+    if (j & ((1 << R0) | (1 << R1))) continue;
+    const int i0 = j, i1 = j | (1 << R1), i2 = j | (1 << R0), i3 = j | (1 << R0) | (1 << R1);
+    if (XX) {
+      acc += cjmul(l[i0], p[i3]).y + cjmul(l[i3], p[i0]).y + cjmul(l[i1], p[i2]).y + cjmul(l[i2], p[i1]).y;
+    } else {
+      acc += cjmul(l[i0], p[i0]).y - cjmul(l[i1], p[i1]).y - cjmul(l[i2], p[i2]).y + cjmul(l[i3], p[i3]).y;
+    }
+  }
+  return acc;
+}
+
 template <typename T>
 __device__ __forceinline__ cplx<T> pauli_row(int code, int bit, cplx<T> a, cplx<T> b, T &sgn) {
   // returns (P psi) component for bit value `bit`, given psi components a (0) and b (1)
@@ -675,6 +737,41 @@ __device__ __forceinline__ void u2_dispatch(cplx<T> (&v)[NREG], kptr<cplx<T>> m,
     TQS_U2_CASES(X)
 #undef X
   }
+}
+
+template <typename T, bool ADJ, int KIND>
+__device__ __forceinline__ void u2s_dispatch_k(cplx<T> (&v)[NREG], kptr<cplx<T>> m, int r0, int r1) {
+  switch (r0 * 4 + r1) {
+#define X(a, b) \
+  case a * 4 + b: TQS_CASE_MARK(s##a##b##_##KIND); u2s_apply<T, a, b, ADJ, KIND>(v, m); TQS_CASE_MARK(es##a##b##_##KIND); break;
+    TQS_U2_CASES(X)
+#undef X
+  }
+}
+
+template <typename T, bool ADJ>
+__device__ __forceinline__ void u2_apply_any(cplx<T> (&v)[NREG], kptr<cplx<T>> m, int r0, int r1, int sub) {
+  switch (sub) {
+    case U2_CNOT: u2s_dispatch_k<T, ADJ, U2_CNOT>(v, m, r0, r1); break;
+    case U2_SWAP: u2s_dispatch_k<T, ADJ, U2_SWAP>(v, m, r0, r1); break;
+    case U2_CZ: u2s_dispatch_k<T, ADJ, U2_CZ>(v, m, r0, r1); break;
+    case U2_MS: u2s_dispatch_k<T, ADJ, U2_MS>(v, m, r0, r1); break;
+    case U2_ECR: u2s_dispatch_k<T, ADJ, U2_ECR>(v, m, r0, r1); break;
+    case U2_DIAG: u2s_dispatch_k<T, ADJ, U2_DIAG>(v, m, r0, r1); break;
+    default: u2_dispatch<T, ADJ>(v, m, r0, r1); break;
+  }
+}
+
+template <typename T, bool XX>
+__device__ __forceinline__ T u2s_grad_dispatch(const cplx<T> (&p)[NREG], const cplx<T> (&l)[NREG], int r0,
+                                               int r1) {
+  switch (r0 * 4 + r1) {
+#define X(a, b) \
+  case a * 4 + b: { TQS_CASE_MARK(g##a##b##_##XX); const T r_ = u2s_grad<T, a, b, XX>(p, l); TQS_CASE_MARK(eg##a##b##_##XX); return r_; }
+    TQS_U2_CASES(X)
+#undef X
+  }
+  return T(0);
 }
 
 template <typename T>
@@ -879,11 +976,17 @@ __device__ __forceinline__ void run_stage(const Ctx<T, K> &c, const PassArgs<T> 
     } else if (op.kind == OP_U2) {
       kptr<cplx<T>> mg = op_mat(a, op, s_thr);
       if (BWD && (op.flags & F_GRAD)) {
-        const T g = u2_grad_dispatch(vp, vl, op.r0, op.r1, op.aux);
+        T g;
+        if (op.aux == (1 | (1 << 2)))
+          g = u2s_grad_dispatch<T, true>(vp, vl, op.r0, op.r1);
+        else if (op.aux == (3 | (3 << 2)))
+          g = u2s_grad_dispatch<T, false>(vp, vl, op.r0, op.r1);
+        else
+          g = u2_grad_dispatch(vp, vl, op.r0, op.r1, op.aux);
         write_acc(c, a, g, op.acc);
       }
-      u2_dispatch<T, BWD>(vp, mg, op.r0, op.r1);
-      if (BWD) u2_dispatch<T, true>(vl, mg, op.r0, op.r1);
+      u2_apply_any<T, BWD>(vp, mg, op.r0, op.r1, op.sub);
+      if (BWD) u2_apply_any<T, true>(vl, mg, op.r0, op.r1, op.sub);
     } else if (op.kind == OP_DIAG) {
       kptr<DevDiag> dg = a.diags + uni(a.pass->diag_begin) + op.aux;
       const DiagView dv = diag_view(dg);
@@ -1286,27 +1389,35 @@ __global__ void __launch_bounds__(NTE) k_expval(ReadArgs<T> a) {
   }
 }
 
+// Sum of a double across the 64 lanes of a wave, in a fixed order; valid in lane 63.
+__device__ __forceinline__ double wave_sum(double v) { return seg_sum_dpp(v, 6); }
+
 // expz[b, i] and norm[b] from the partials; wire i <-> state bit p = n-1-i.
-__global__ void k_expval_final(const double *partials, double *expz, double *norm, int n, int batch) {
-  const int idx = blockIdx.x * blockDim.x + threadIdx.x;
-  if (idx >= batch * (n + 1)) return;
-  const int b = idx / (n + 1), i = idx % (n + 1);
+// One wave per output (b, i); i == n gives the norm.
+__global__ void __launch_bounds__(64) k_expval_final(const double *partials, double *expz, double *norm, int n,
+                                                     int batch) {
+  const int b = blockIdx.x / (n + 1), i = blockIdx.x % (n + 1);
+  const int lane = threadIdx.x;
   const long long units = n > KE ? (1ll << (n - KE)) : 1;
-  double s = 0.0;
-  if (i == n) {
-    for (long long u = 0; u < units; ++u) s += partials[((long long)b * units + u) * (KE + 1)];
-    if (norm) norm[b] = s;
-    return;
-  }
   const int p = n - 1 - i;
-  for (long long u = 0; u < units; ++u) {
+  double s = 0.0;
+  for (long long u = lane; u < units; u += 64) {
     const double *q = partials + ((long long)b * units + u) * (KE + 1);
-    if (p < KE)
+    if (i == n)
+      s += q[0];
+    else if (p < KE)
       s += q[1 + p];
     else
       s += ((u >> (p - KE)) & 1) ? -q[0] : q[0];
   }
-  expz[(long long)b * n + i] = s;
+  s = wave_sum(s);
+  if (lane == 63) {
+    if (i == n) {
+      if (norm) norm[b] = s;
+    } else {
+      expz[(long long)b * n + i] = s;
+    }
+  }
 }
 
 // lambda = psi * h with h(j) = sum_i g_i (1 - 2 b_i(j)), per sample
@@ -1343,18 +1454,18 @@ __global__ void __launch_bounds__(NTE) k_adj_init(ReadArgs<T> a) {
   }
 }
 
-// A[acc][b] = sum of the pass partials of sample b (FP64, fixed order)
+// A[acc][b] = sum of the pass partials of sample b (FP64, fixed order); one wave per (acc, b).
 template <typename T>
-__global__ void k_acc_reduce(const T *partials, const long long *acc_static, const int *acc_units,
-                             int n_acc, int batch, double *A) {
-  const long long idx = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (idx >= (long long)n_acc * batch) return;
+__global__ void __launch_bounds__(64) k_acc_reduce(const T *partials, const long long *acc_static,
+                                                   const int *acc_units, int n_acc, int batch, double *A) {
+  const long long idx = blockIdx.x;
   const int acc = (int)(idx / batch), b = (int)(idx % batch);
   const int U = acc_units[acc];
   const T *p = partials + acc_static[acc] * batch + (long long)b * U;
   double s = 0.0;
-  for (int u = 0; u < U; ++u) s += (double)p[u];
-  A[idx] = s;
+  for (int u = threadIdx.x; u < U; u += 64) s += (double)p[u];
+  s = wave_sum(s);
+  if (threadIdx.x == 63) A[idx] = s;
 }
 
 // gradients: weights sum over samples; features per sample

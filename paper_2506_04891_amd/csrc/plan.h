@@ -41,6 +41,17 @@ enum OpFlag : int32_t {
   F_DIAGONAL = 8,    // U1/U2 matrix is diagonal
 };
 
+// Structure of a 4x4 op, chosen by the planner from the gate.
+enum U2Kind : int32_t {
+  U2_GEN = 0,    // dense complex 4x4
+  U2_CNOT = 1,   // swap |10> <-> |11>
+  U2_SWAP = 2,   // swap |01> <-> |10>
+  U2_CZ = 3,     // negate |11>
+  U2_MS = 4,     // cos(pi t) I - i sin(pi t) X(x)X
+  U2_ECR = 5,    // (I(x)X - X(x)Y) / sqrt(2)
+  U2_DIAG = 6,   // diagonal
+};
+
 struct DevOp {
   int32_t kind;
   int32_t flags;
@@ -48,7 +59,7 @@ struct DevOp {
   int32_t mat;       // matrix offset in complex elements (U1: 4, U2: 16 entries)
   int32_t acc;       // first gradient accumulator of the pass, -1 if none
   int32_t aux;       // U2 grad: Pauli code pa | pb<<2 (1=X,2=Y,3=Z); DIAG: diag index; PERM: perm index
-  int32_t pad;
+  int32_t sub;       // U2: U2Kind
 };
 
 struct DevStage {

@@ -938,6 +938,11 @@ static std::string emit(Plan &P) {
         o.r1 = ridx(tix.at(op.bits[1]));
         o.mat = op_mat[oi_ir];
         o.flags = (op.per_sample ? F_PERSAMPLE : 0);
+        {
+          const int g = P.factors[op.factors[0]].gate;
+          o.sub = g == CNOT ? U2_CNOT : g == SWAP ? U2_SWAP : g == CZ ? U2_CZ : g == MS ? U2_MS
+                : g == ECR ? U2_ECR : g == ZZ ? U2_DIAG : U2_GEN;
+        }
         if (op.has_grad) {
           const Factor &f = P.factors[op.factors[0]];
           o.flags |= F_GRAD;

@@ -235,14 +235,33 @@ struct ProfScope {
   }
 };
 
-// Algorithmic flops of one op application on one amplitude (forward).
+// Algorithmic flops of one op application on one amplitude (forward): a
+// complex multiply is 6 flops, a complex add 2.  U1: two complex products and
+// one add per output (14), real matrix 6, diagonal 6; U2 dense: four products
+// and three adds (30), MS 6, ECR 6 (two complex adds and one scaling), CZ 2,
+// CNOT / SWAP 0; split-table diagonal: two complex products (12).
 double op_flops(const DevOp &o) {
   switch (o.kind) {
-    case OP_U1: return (o.flags & F_DIAGONAL) ? 6.0 : ((o.flags & F_REAL) ? 8.0 : 16.0);
-    case OP_U2: return 32.0;
+    case OP_U1: return (o.flags & F_DIAGONAL) ? 6.0 : ((o.flags & F_REAL) ? 6.0 : 14.0);
+    case OP_U2:
+      switch (o.sub) {
+        case U2_CNOT: case U2_SWAP: return 0.0;
+        case U2_CZ: return 2.0;
+        case U2_MS: case U2_ECR: case U2_DIAG: return 6.0;
+        default: return 30.0;
+      }
     case OP_DIAG: return 12.0;
     default: return 0.0;
   }
+}
+
+// Backward flops of an op per amplitude: psi and lambda are both uncomputed
+// (2x forward) and ops with parameters add their gradient sums (U1: three
+// Pauli sums over pairs, 6 flops per amplitude each; U2 / diagonal: one sum).
+double op_flops_bwd(const DevOp &o) {
+  double f = 2.0 * op_flops(o);
+  if (o.flags & F_GRAD) f += (o.kind == OP_U1) ? 18.0 : 8.0;
+  return f;
 }
 
 template <typename T, int K, bool BWD>
@@ -289,9 +308,12 @@ tqs_status launch_pass(tqs_circuit *c, int pi, int B, const cplx<T> *src0, cplx<
       bytes = amps * es * ((d.load_mode == LOAD_GLOBAL ? 1.0 : 0.0) + 1.0);
     double f = 0;
     for (int st = d.stage_begin; st < d.stage_begin + d.n_stages; ++st)
-      for (int oi = P.dstage[st].op_begin; oi < P.dstage[st].op_end; ++oi) f += op_flops(P.dop[oi]);
-    // backward: both states are uncomputed, plus the gradient sums (~1x)
-    flops = amps * f * (BWD ? 3.0 : 1.0);
+      for (int oi = P.dstage[st].op_begin; oi < P.dstage[st].op_end; ++oi)
+        f += BWD ? op_flops_bwd(P.dop[oi]) : op_flops(P.dop[oi]);
+    if (BWD)
+      for (int st = d.grad_stage_begin; st < d.grad_stage_begin + d.n_grad_stages; ++st)
+        f += 18.0 * (P.dstage[st].op_end - P.dstage[st].op_begin);
+    flops = amps * f;
   }
   ProfScope ps(c, s, std::string(BWD ? "pass_bwd_K" : "pass_fwd_K") + std::to_string(d.K) +
                          (sizeof(T) == 8 ? "_c128" : "_c64"), bytes, flops);
@@ -382,7 +404,7 @@ tqs_status expval_t(const tqs_circuit *c, int B, const void *state, double *expz
   ps.end();
   HIP_TRY(hipGetLastError());
   const int tot = B * (P.n + 1);
-  hipLaunchKernelGGL(k_expval_final, dim3((tot + 255) / 256), dim3(256), 0, s,
+  hipLaunchKernelGGL(k_expval_final, dim3(tot), dim3(64), 0, s,
                      (const double *)(ws + L.ev), expz, norm, P.n, B);
   HIP_TRY(hipGetLastError());
   return TQS_OK;
@@ -435,7 +457,7 @@ tqs_status adjoint_t(tqs_circuit *c, int B, const double *w, const double *x, vo
   ProfScope psf(c, s, "grad_finalize", 0.0, 0.0);
   if (P.n_acc > 0) {
     const long long tot = (long long)P.n_acc * B;
-    hipLaunchKernelGGL((k_acc_reduce<T>), dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s,
+    hipLaunchKernelGGL((k_acc_reduce<T>), dim3((unsigned)tot), dim3(64), 0, s,
                        reinterpret_cast<const T *>(ws + L.partials), (const long long *)c->d_acc_static,
                        (const int *)c->d_acc_units, P.n_acc, B, A);
     HIP_TRY(hipGetLastError());

@@ -1,0 +1,504 @@
+"""Continuous-batching request loop for circuit evaluations.
+
+Requests (a circuit, its weights, a batch of input rows, forward-only or
+forward + gradient) arrive at any time.  A scheduler thread
+
+* queues them per *group key* -- (qubits, layer structure, want_grad) -- so
+  that requests with the same circuit structure share one launch even when their
+  weights differ: the serving circuit reads every parameter from its input
+  rows (weights become extra per-row columns), so one launch evaluates rows of
+  many requests;
+* admits work while the device memory it would reserve (state, workspace,
+  inputs, outputs of the padded batch) fits a byte budget and a stream is free;
+* runs each launch on one of K streams, so launches of different keys overlap
+  on the device, replaying a captured HIP graph for small circuits (launch
+  latency dominates there), and frees the reservation when the launch's event
+  completes, admitting waiting requests as memory and streams free up;
+* records arrival -> result latency per request.
+
+``Server(..., plain=True)`` is the plain per-request path used as the
+baseline: one stream, FIFO, one request per launch, no graphs, each launch
+synchronised before the next starts.
+
+The scheduler only needs an *executor* with ``reserve(group)``, ``launch(group,
+slot)`` and ``poll(handle)``; ``GpuExecutor`` drives libtqsim, and tests use a
+host-only executor to check the scheduling logic.
+"""
+from __future__ import annotations
+
+import collections
+import math
+import threading
+import time
+from concurrent.futures import Future
+
+import numpy as np
+
+
+class Request:
+    """One evaluation request.
+
+    layers: the circuit's layer list (weights addressed as WEIGHT, inputs as INPUT)
+    n: qubits; weights: [n_weights] float64; features: [batch, n_features] float64
+    want_grad: also return gradients of sum_i g_i <Z_i> (g = upstream or ones)."""
+
+    __slots__ = ("rid", "n", "layers", "weights", "features", "want_grad", "upstream",
+                 "t_arrive", "t_done", "future", "key")
+
+    def __init__(self, n, layers, weights, features, want_grad=False, upstream=None, rid=None):
+        self.rid = rid
+        self.n = int(n)
+        self.layers = list(layers)
+        self.weights = np.ascontiguousarray(weights, dtype=np.float64).reshape(-1)
+        self.features = np.ascontiguousarray(features, dtype=np.float64)
+        if self.features.ndim == 1:
+            self.features = self.features[None, :]
+        self.want_grad = bool(want_grad)
+        self.upstream = None if upstream is None else np.asarray(upstream, dtype=np.float64)
+        self.t_arrive = None
+        self.t_done = None
+        self.future = Future()
+        self.key = (self.n, structure_key(self.layers), self.want_grad)
+
+    @property
+    def batch(self):
+        return self.features.shape[0]
+
+
+class Result:
+    __slots__ = ("expz", "grad_weights", "grad_features", "latency")
+
+    def __init__(self, expz, grad_weights=None, grad_features=None, latency=None):
+        self.expz, self.grad_weights, self.grad_features, self.latency = expz, grad_weights, grad_features, latency
+
+
+def structure_key(layers):
+    """Circuit structure without parameter values (sources and offsets kept)."""
+    return tuple((ly.gate, ly.pattern, ly.source, ly.wire, ly.wire2, ly.offset,
+                  ly.fixed if ly.source == "FIXED" else 0.0) for ly in layers)
+
+
+def bucket(b):
+    """Batch buckets: powers of two (graphs are reused across requests)."""
+    return 1 << max(0, int(math.ceil(math.log2(max(1, b)))))
+
+
+class Group:
+    """Requests launched together."""
+
+    def __init__(self, key, reqs):
+        self.key = key
+        self.reqs = reqs
+        self.rows = sum(r.batch for r in reqs)
+        self.reserve = 0
+        self.handle = None
+        self.slot = None
+
+
+class Server:
+    """Scheduler thread over an executor.
+
+    budget_bytes: device memory that admitted launches may reserve together.
+    streams: launches in flight at once.  max_rows: rows per coalesced launch.
+    plain: the per-request baseline (one stream, FIFO, no coalescing)."""
+
+    def __init__(self, executor, budget_bytes, streams=4, max_rows=1024, plain=False, poll_s=50e-6,
+                 paused=False):
+        self.ex = executor
+        self._paused = paused
+        self.budget = int(budget_bytes)
+        self.streams = 1 if plain else int(streams)
+        self.max_rows = int(max_rows)
+        self.plain = plain
+        self.poll_s = poll_s
+        self._lock = threading.Lock()
+        self._cv = threading.Condition(self._lock)
+        self._pending = collections.OrderedDict()   # key -> deque of requests (FIFO per key)
+        self._order = collections.deque()            # arrival order of keys with pending work
+        self._inflight = []
+        self._free_slots = list(range(self.streams))
+        self._reserved = 0
+        self._stop = False
+        self.completed = []
+        self.errors = []
+        self.peak_reserved = 0
+        self.launches = 0
+        self._thread = threading.Thread(target=self._loop, name="tqs-serve", daemon=True)
+        self._thread.start()
+
+    # ------------------------------------------------------------- client --
+    def submit(self, req: Request) -> Future:
+        need = self.ex.reserve(Group(req.key, [req]))
+        if need > self.budget:
+            req.future.set_exception(MemoryError(
+                f"request needs {need} bytes of device memory, budget is {self.budget}"))
+            return req.future
+        with self._cv:
+            req.t_arrive = time.perf_counter()
+            q = self._pending.get(req.key)
+            if q is None:
+                q = self._pending[req.key] = collections.deque()
+            q.append(req)
+            self._order.append(req.key)
+            self._cv.notify()
+        return req.future
+
+    def resume(self):
+        """Start admitting work (a server created with paused=True queues only)."""
+        with self._cv:
+            self._paused = False
+            self._cv.notify()
+
+    def close(self, wait=True):
+        if wait:
+            self.resume()
+            self.drain()
+        with self._cv:
+            self._stop = True
+            self._cv.notify()
+        self._thread.join()
+
+    def drain(self, timeout=None):
+        t0 = time.perf_counter()
+        while True:
+            with self._lock:
+                if not self._inflight and not any(self._pending.values()):
+                    return
+            if timeout is not None and time.perf_counter() - t0 > timeout:
+                raise TimeoutError("serving queue did not drain")
+            time.sleep(self.poll_s)
+
+    def stats(self):
+        lat = np.array([r.t_done - r.t_arrive for r in self.completed]) if self.completed else np.zeros(1)
+        evals = sum(r.batch for r in self.completed)
+        span = (max(r.t_done for r in self.completed) - min(r.t_arrive for r in self.completed)
+                if self.completed else 0.0)
+        return {"requests": len(self.completed), "evals": evals,
+                "p50_ms": float(np.percentile(lat, 50) * 1e3), "p99_ms": float(np.percentile(lat, 99) * 1e3),
+                "mean_ms": float(lat.mean() * 1e3), "evals_per_s": evals / span if span > 0 else 0.0,
+                "launches": self.launches, "peak_reserved_bytes": self.peak_reserved,
+                "errors": len(self.errors)}
+
+    # ---------------------------------------------------------- scheduler --
+    def _next_group(self):
+        """Oldest pending key; its requests up to max_rows (one request when plain)."""
+        while self._order:
+            key = self._order[0]
+            q = self._pending.get(key)
+            if not q:
+                self._order.popleft()
+                continue
+            reqs = [q.popleft()]
+            if not self.plain:
+                rows = reqs[0].batch
+                while q and rows + q[0].batch <= self.max_rows:
+                    rows += q[0].batch
+                    reqs.append(q.popleft())
+            # keep arrival order: drop this key's entries that were consumed
+            self._order.popleft()
+            return Group(key, reqs)
+        return None
+
+    def _requeue_front(self, g):
+        q = self._pending.setdefault(g.key, collections.deque())
+        for r in reversed(g.reqs):
+            q.appendleft(r)
+        self._order.appendleft(g.key)
+
+    def _loop(self):
+        while True:
+            with self._cv:
+                if self._stop:
+                    return
+                # completions
+                still = []
+                for g in self._inflight:
+                    done = False
+                    try:
+                        done = self.ex.poll(g.handle)
+                    except Exception as e:  # device / executor failure: fail the group
+                        self._fail(g, e)
+                        continue
+                    if done:
+                        self._finish(g)
+                    else:
+                        still.append(g)
+                self._inflight = still
+                # admission
+                while not self._paused and self._free_slots and (not self.plain or not self._inflight):
+                    g = self._next_group()
+                    if g is None:
+                        break
+                    g.reserve = self.ex.reserve(g)
+                    avail = self.budget - self._reserved
+                    # shrink a coalesced group until it fits the free budget
+                    while g.reserve > avail and len(g.reqs) > 1:
+                        last = g.reqs.pop()
+                        g.rows -= last.batch
+                        self._pending[g.key].appendleft(last)
+                        self._order.appendleft(g.key)
+                        g.reserve = self.ex.reserve(g)
+                    if g.reserve > avail:
+                        self._requeue_front(g)     # wait for memory to free up
+                        break
+                    g.slot = self._free_slots.pop()
+                    self._reserved += g.reserve
+                    self.peak_reserved = max(self.peak_reserved, self._reserved)
+                    try:
+                        g.handle = self.ex.launch(g, g.slot)
+                        self.launches += 1
+                        self._inflight.append(g)
+                    except Exception as e:
+                        self._fail(g, e)
+                if not self._inflight and not any(self._pending.values()):
+                    self._cv.wait(timeout=0.01)
+                    continue
+            if self.plain and self._inflight:
+                # the plain path waits for its one launch before the next
+                try:
+                    self.ex.wait(self._inflight[0].handle)
+                except Exception:
+                    pass
+            else:
+                time.sleep(self.poll_s)
+
+    def _release(self, g):
+        self._reserved -= g.reserve
+        self._free_slots.append(g.slot)
+
+    def _finish(self, g):
+        self._release(g)
+        try:
+            results = self.ex.results(g.handle)
+        except Exception as e:
+            self._fail(g, e, released=True)
+            return
+        t = time.perf_counter()
+        for r, res in zip(g.reqs, results):
+            r.t_done = t
+            res.latency = t - r.t_arrive
+            self.completed.append(r)
+            r.future.set_result(res)
+
+    def _fail(self, g, e, released=False):
+        if not released and g.slot is not None:
+            self._release(g)
+        self.errors.append(repr(e))
+        for r in g.reqs:
+            if not r.future.done():
+                r.future.set_exception(e)
+
+
+# ---------------------------------------------------------------- executor --
+
+def serving_layers(layers, n):
+    """The same circuit reading every weight from its input rows: WEIGHT layers
+    become INPUT layers whose columns follow the request's own feature columns."""
+    from .tqsim import Circuit  # noqa: F401  (kept for the binding's enum names)
+    nf = 0
+    for ly in layers:
+        if ly.source == "INPUT":
+            nf = max(nf, ly.offset + _count(ly, n))
+    out = []
+    for ly in layers:
+        if ly.source == "WEIGHT":
+            out.append(ly._replace(source="INPUT", offset=nf + ly.offset))
+        else:
+            out.append(ly)
+    return out, nf
+
+
+def _count(ly, n):
+    if ly.gate in ("RX", "RY", "RZ", "H", "X", "Z", "S", "SX", "GPI", "GPI2"):
+        return n if ly.pattern == "ALL" else 1
+    if ly.pattern == "WIRE":
+        return 1
+    if ly.pattern == "RING":
+        return 0 if n < 2 else (1 if n == 2 else n)
+    if ly.pattern == "CHAIN":
+        return n - 1
+    return n // 2
+
+
+class HostExecutor:
+    """Executes groups on the host with a caller-supplied function (scheduler
+    tests): fn(request) -> Result.  ``delay`` seconds per launch emulate device
+    time; ``row_bytes`` sets the reservation per padded row; ``fail_on`` makes
+    launches of requests with those ids raise."""
+
+    def __init__(self, fn, delay=0.0, row_bytes=1 << 20, fail_on=()):
+        self.fn, self.delay, self.row_bytes, self.fail_on = fn, delay, row_bytes, set(fail_on)
+        self.launched = []
+        self.max_concurrent = 0
+        self._live = 0
+
+    def reserve(self, g):
+        return bucket(g.rows) * self.row_bytes
+
+    def launch(self, g, slot):
+        if any(r.rid in self.fail_on for r in g.reqs):
+            raise RuntimeError("device failure injected for request(s) %s" % [r.rid for r in g.reqs])
+        self.launched.append([r.rid for r in g.reqs])
+        self._live += 1
+        self.max_concurrent = max(self.max_concurrent, self._live)
+        return {"g": g, "t": time.perf_counter() + self.delay}
+
+    def poll(self, h):
+        return time.perf_counter() >= h["t"]
+
+    def wait(self, h):
+        while not self.poll(h):
+            time.sleep(1e-4)
+
+    def results(self, h):
+        self._live -= 1
+        return [self.fn(r) for r in h["g"].reqs]
+
+
+class GpuExecutor:
+    """Runs groups through libtqsim on K HIP streams (default priority)."""
+
+    def __init__(self, streams=4, graphs=True, graph_max_qubits=14, device="cuda"):
+        import torch
+        self.torch = torch
+        self.device = torch.device(device)
+        self.streams = [torch.cuda.Stream(device=self.device) for _ in range(streams)]
+        self.graphs = graphs
+        self.graph_max_qubits = graph_max_qubits
+        self._circuits = {}
+        self._graphs = {}      # (key, B) -> list of [graph, static tensors, busy]
+        self._lock = threading.Lock()
+
+    def _circuit(self, key, layers, n):
+        c = self._circuits.get(key)
+        if c is None:
+            from .tqsim import Circuit
+            sl, nf = serving_layers(layers, n)
+            c = Circuit(n, sl, "c64")
+            c._serve_nx = nf
+            self._circuits[key] = c
+        return c
+
+    def reserve(self, g):
+        r0 = g.reqs[0]
+        B = bucket(g.rows)
+        c = self._circuit(g.key, r0.layers, r0.n)
+        cols = max(1, c.n_features)
+        return (c.workspace_size(B, g.key[2]) + (B << r0.n) * 8
+                + B * cols * 8 * (2 if g.key[2] else 1) + B * (r0.n + 1) * 8 * 2)
+
+    def _rows(self, g, c):
+        nx = c._serve_nx
+        cols = c.n_features
+        X = np.zeros((bucket(g.rows), max(1, cols)), dtype=np.float64)
+        G = np.zeros((bucket(g.rows), g.reqs[0].n), dtype=np.float64)
+        row = 0
+        for r in g.reqs:
+            b = r.batch
+            if nx:
+                X[row:row + b, :nx] = r.features[:, :nx]
+            if cols > nx:
+                X[row:row + b, nx:cols] = r.weights[None, : cols - nx]
+            G[row:row + b] = 1.0 if r.upstream is None else r.upstream
+            row += b
+        return X, G
+
+    def launch(self, g, slot):
+        torch = self.torch
+        r0 = g.reqs[0]
+        c = self._circuit(g.key, r0.layers, r0.n)
+        X, G = self._rows(g, c)
+        B = X.shape[0]
+        stream = self.streams[slot]
+        h = {"group": g, "circ": c, "event": torch.cuda.Event(), "stream": stream}
+        with torch.cuda.stream(stream):
+            xp = torch.from_numpy(X).pin_memory()
+            gp = torch.from_numpy(G).pin_memory()
+            use_graph = self.graphs and r0.n <= self.graph_max_qubits
+            entry = self._graph_entry(c, g.key, B, stream) if use_graph else None
+            if entry is not None:
+                st = entry["static"]
+                st["x"].copy_(xp, non_blocking=True)
+                st["g"].copy_(gp, non_blocking=True)
+                entry["graph"].replay()
+                e, gx = st["e"], st.get("gx")
+                h["entry"] = entry
+            else:
+                x = xp.to(self.device, non_blocking=True)
+                gd = gp.to(self.device, non_blocking=True)
+                e, gx = self._run(c, x, gd, g.key[2])
+                h["keep"] = (x, gd)
+            e_h = torch.empty(e.shape, dtype=e.dtype, pin_memory=True)
+            e_h.copy_(e, non_blocking=True)
+            h["e"] = e_h
+            if gx is not None:
+                gx_h = torch.empty(gx.shape, dtype=gx.dtype, pin_memory=True)
+                gx_h.copy_(gx, non_blocking=True)
+                h["gx"] = gx_h
+            h["event"].record(stream)
+        return h
+
+    def _run(self, c, x, g, want_grad, w=None):
+        torch = self.torch
+        B = x.shape[0]
+        ws = torch.empty(c.workspace_size(B, want_grad), dtype=torch.uint8, device=self.device)
+        state = torch.empty((B, 2 ** c.n), dtype=torch.complex64, device=self.device)
+        if w is None:
+            w = torch.zeros(1, dtype=torch.float64, device=self.device)
+        c.forward(w, x, state=state, ws=ws)
+        e = c.expval_z(state, ws=ws)
+        gx = None
+        if want_grad:
+            _, gx = c.adjoint_grad(w, x, state, g, ws=ws)
+        return e, gx
+
+    def _graph_entry(self, c, key, B, stream):
+        """A free captured graph for (key, B), capturing one on first use."""
+        torch = self.torch
+        with self._lock:
+            pool = self._graphs.setdefault((key, B), [])
+            for ent in pool:
+                if not ent["busy"]:
+                    ent["busy"] = True
+                    return ent
+            if len(pool) >= len(self.streams):
+                return None
+        static = {"x": torch.zeros((B, max(1, c.n_features)), dtype=torch.float64, device=self.device),
+                  "g": torch.zeros((B, c.n), dtype=torch.float64, device=self.device),
+                  "w": torch.zeros(1, dtype=torch.float64, device=self.device)}
+        # warm-up outside capture uploads the plan and sizes the allocator
+        e, gx = self._run(c, static["x"], static["g"], key[2], static["w"])
+        torch.cuda.current_stream().synchronize()
+        graph = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(graph, stream=stream):
+            e, gx = self._run(c, static["x"], static["g"], key[2], static["w"])
+        static["e"], static["gx"] = e, gx
+        ent = {"graph": graph, "static": static, "busy": True}
+        with self._lock:
+            pool.append(ent)
+        return ent
+
+    def poll(self, h):
+        return h["event"].query()
+
+    def wait(self, h):
+        h["event"].synchronize()
+
+    def results(self, h):
+        g, c = h["group"], h["circ"]
+        if "entry" in h:
+            with self._lock:
+                h["entry"]["busy"] = False
+        e = h["e"].numpy()
+        gx = h["gx"].numpy() if "gx" in h else None
+        nx = c._serve_nx
+        out, row = [], 0
+        for r in g.reqs:
+            b = r.batch
+            res = Result(e[row:row + b].copy())
+            if gx is not None:
+                res.grad_features = gx[row:row + b, :nx].copy()
+                res.grad_weights = gx[row:row + b, nx:c.n_features].sum(axis=0)
+            out.append(res)
+            row += b
+        return out
