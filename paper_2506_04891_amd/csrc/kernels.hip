@@ -310,6 +310,7 @@ struct PrepArgs {
   double *dbl;       // angles and coefficients (shared)
   double *dbl_ps;    // per-sample
   int dbl_ps_stride;
+  int nv;            // dense layer matrices are 2^nv x 2^nv
 };
 
 __device__ __forceinline__ PrepItem ld_item(kptr<PrepItem> p) {
@@ -327,6 +328,7 @@ __device__ __forceinline__ Factor ld_factor(kptr<Factor> p) {
   f.gate = p->gate;
   f.src = p->src;
   f.pidx = p->pidx;
+  f.wires = p->wires;
   f.fixed = p->fixed;
   return f;
 }
@@ -337,7 +339,11 @@ __global__ void __launch_bounds__(64) k_prep(PrepArgs<T> a) {
   const int b = blockIdx.x * 64 + threadIdx.x;
   if (item >= a.n_items) return;
   const PrepItem it = ld_item(a.items + item);
-  if (it.per_sample ? (b >= a.batch) : (b != 0)) return;
+  if (it.kind == PREP_DENSE) {
+    if (b >= (1 << a.nv)) return;   // one thread per matrix column
+  } else if (it.per_sample ? (b >= a.batch) : (b != 0)) {
+    return;
+  }
   const int bs = it.per_sample ? b : 0;
   switch (it.kind) {
     case PREP_MAT1: {
@@ -407,6 +413,44 @@ __global__ void __launch_bounds__(64) k_prep(PrepArgs<T> a) {
       c *= -2.0 / (double)(1 << nb);
       double *o = it.per_sample ? a.dbl_ps + (size_t)bs * a.dbl_ps_stride + it.out : a.dbl + it.out;
       o[0] = c;
+      break;
+    }
+    case PREP_DENSE: {
+      // column `b` of the layer's full matrix: apply the layer's gates, in
+      // order, to the basis vector e_b (FP64), write U[:, b] rounded to dtype
+      const int dim = 1 << a.nv;
+      zd v[64];
+      for (int j = 0; j < dim; ++j) v[j] = zmk(j == b ? 1.0 : 0.0, 0.0);
+      for (int k = it.f_begin; k < it.f_end; ++k) {
+        const Factor fc = ld_factor(a.factors + k);
+        const double th = factor_param(fc, a.w, a.x, a.nfeat, 0);
+        const int p0 = fc.wires & 0xff, p1 = (fc.wires >> 8) - 1;
+        if (p1 < 0) {
+          zd m[4], d[4];
+          gate2(fc.gate, th, m, d);
+          for (int j = 0; j < dim; ++j) {
+            if ((j >> p0) & 1) continue;
+            const zd x0 = v[j], x1 = v[j | (1 << p0)];
+            v[j] = zadd(zmul(m[0], x0), zmul(m[1], x1));
+            v[j | (1 << p0)] = zadd(zmul(m[2], x0), zmul(m[3], x1));
+          }
+        } else {
+          zd m[16];
+          gate4(fc.gate, th, m);
+          for (int j = 0; j < dim; ++j) {
+            if (((j >> p0) & 1) || ((j >> p1) & 1)) continue;
+            const int q[4] = {j, j | (1 << p1), j | (1 << p0), j | (1 << p0) | (1 << p1)};
+            zd x[4] = {v[q[0]], v[q[1]], v[q[2]], v[q[3]]};
+            for (int r = 0; r < 4; ++r) {
+              zd acc = zmk(0, 0);
+              for (int cc = 0; cc < 4; ++cc) acc = zadd(acc, zmul(m[r * 4 + cc], x[cc]));
+              v[q[r]] = acc;
+            }
+          }
+        }
+      }
+      cplx<T> *o = a.mats + it.out;
+      for (int j = 0; j < dim; ++j) o[(long long)j * dim + b] = cmk<T>((T)v[j].x, (T)v[j].y);
       break;
     }
   }
@@ -885,11 +929,84 @@ __device__ __forceinline__ cplx<T> diag_phase(const DiagView &d, const cplx<T> *
   return cmul(tab[d.lds_off + il], tab[d.th_off + (t >> d.h)]);
 }
 
+// MFMA 16x16x4 (f32 and f64).  Operands: lane l holds A[l%16][l/16] and
+// B[l/16][l%16]; result register r of lane l is D[4*(l/16)+r][l%16] for f32
+// and D[(l/16)+4r][l%16] for f64.
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef double f64x4 __attribute__((ext_vector_type(4)));
+template <typename T>
+struct Mfma;
+template <>
+struct Mfma<float> {
+  typedef f32x4 V;
+  static __device__ __forceinline__ V run(float a, float b, V c) {
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+  }
+  static __device__ __forceinline__ int row(int lane, int r) { return 4 * (lane >> 4) + r; }
+};
+template <>
+struct Mfma<double> {
+  typedef f64x4 V;
+  static __device__ __forceinline__ V run(double a, double b, V c) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+  }
+  static __device__ __forceinline__ int row(int lane, int r) { return (lane >> 4) + 4 * r; }
+};
+
+// X <- U X (or U^dagger X) for every sample of the tile: out[j][s] =
+// sum_k U[j][k] X[k][s], X[k][s] = tile element s * 2^nv + k.  Complex products
+// as four real MFMA products; 16 x 16 output blocks spread over the waves;
+// results go to the scratch tile S, then back to X.
+template <typename T, int K, bool ADJ>
+__device__ __forceinline__ void dense_apply(const Ctx<T, K> &c, cplx<T> *X, cplx<T> *S, kptr<cplx<T>> U) {
+  typedef typename Mfma<T>::V V;
+  constexpr int NT = Ctx<T, K>::NT;
+  const int nv = c.nv;
+  const int dim = 1 << nv;
+  const int rb = dim >> 4, cb = (1 << (K - nv)) >> 4;
+  const int lane = c.tid & 63, wave = c.tid >> 6;
+  for (int blk = wave; blk < rb * cb; blk += NT / 64) {
+    const int mb = blk % rb, nb = blk / rb;
+    V acc_r = {0, 0, 0, 0}, acc_i = {0, 0, 0, 0};
+    const int ar = mb * 16 + (lane & 15);
+    const int bj = nb * 16 + (lane & 15);
+    for (int kb = 0; kb < (dim >> 2); ++kb) {
+      const int kk = kb * 4 + (lane >> 4);
+      cplx<T> u = ADJ ? cconj(kld(U, (long long)kk * dim + ar)) : kld(U, (long long)ar * dim + kk);
+      const cplx<T> x = X[swz<T>(bj * dim + kk)];
+      acc_r = Mfma<T>::run(u.x, x.x, acc_r);
+      acc_r = Mfma<T>::run(-u.y, x.y, acc_r);
+      acc_i = Mfma<T>::run(u.x, x.y, acc_i);
+      acc_i = Mfma<T>::run(u.y, x.x, acc_i);
+    }
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int row = mb * 16 + Mfma<T>::row(lane, r);
+      S[swz<T>(bj * dim + row)] = cmk<T>(acc_r[r], acc_i[r]);
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int i = 0; i < NREG; ++i) {
+    const int t = swz<T>(c.tid + i * NT);
+    X[t] = S[t];
+  }
+  __syncthreads();
+}
+
 template <typename T, int K, bool BWD>
 __device__ __forceinline__ void run_stage(const Ctx<T, K> &c, const PassArgs<T> &a, const UStage &S, cplx<T> *Lp,
                           cplx<T> *Ll, const cplx<T> *tab, bool grad_only) {
   constexpr int NT = Ctx<T, K>::NT;
   const int op0_kind = uni(a.ops[S.op_begin].kind);
+  if (op0_kind == OP_DENSE) {
+    kptr<cplx<T>> U = a.mats + uni(a.ops[S.op_begin].mat);
+    cplx<T> *scr = const_cast<cplx<T> *>(tab) + uni(a.pass->dense_off);
+    __syncthreads();
+    dense_apply<T, K, BWD>(c, Lp, scr, U);
+    if (BWD) dense_apply<T, K, true>(c, Ll, scr, U);
+    return;
+  }
   if (op0_kind == OP_PERM) {
     // in-tile permutation: forward new[t] = old[src(t)], backward the inverse
     kptr<DevPerm> pm = a.perms + uni(a.ops[S.op_begin].aux);
@@ -987,6 +1104,12 @@ __device__ __forceinline__ void run_stage(const Ctx<T, K> &c, const PassArgs<T> 
       }
       u2_apply_any<T, BWD>(vp, mg, op.r0, op.r1, op.sub);
       if (BWD) u2_apply_any<T, true>(vl, mg, op.r0, op.r1, op.sub);
+    } else if (op.kind == OP_GRAD2) {
+      if (BWD && (op.flags & F_GRAD)) {
+        const T g = (op.aux == (1 | (1 << 2))) ? u2s_grad_dispatch<T, true>(vp, vl, op.r0, op.r1)
+                                                : u2s_grad_dispatch<T, false>(vp, vl, op.r0, op.r1);
+        write_acc(c, a, g, op.acc);
+      }
     } else if (op.kind == OP_DIAG) {
       kptr<DevDiag> dg = a.diags + uni(a.pass->diag_begin) + op.aux;
       const DiagView dv = diag_view(dg);

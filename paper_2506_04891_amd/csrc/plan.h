@@ -32,6 +32,8 @@ enum OpKind : int32_t {
   OP_DIAG = 3,   // diagonal phase from split tables (any tile / base bits)
   OP_GRAD1 = 4,  // gradient-only Pauli sums on register bit r0 (no gate)
   OP_PERM = 5,   // in-tile GF(2)-affine permutation (resident passes only)
+  OP_DENSE = 6,  // full 2^nv x 2^nv layer unitary on every sample of the tile (MFMA)
+  OP_GRAD2 = 7,  // gradient-only Pauli-pair sum on register bits (r0, r1) (no gate)
 };
 
 enum OpFlag : int32_t {
@@ -120,8 +122,9 @@ struct DevPass {
   int32_t acc_region;        // offset of this pass's partials (floats)
   int32_t grad_stage_begin, n_grad_stages;   // backward-only tail stages (embed gradients)
   int32_t skip_bwd_store;    // backward of the first pass need not store
-  int32_t diag_lds;          // complex elements of diag tables in LDS
-  int32_t pad[3];
+  int32_t diag_lds;          // complex elements of diag tables (and dense scratch) in LDS
+  int32_t dense_off;         // LDS offset (elements, after the tiles) of the dense-op scratch, -1 if none
+  int32_t pad[2];
 };
 
 // Parameter-preparation program (run on the device per call, FP64).
@@ -132,14 +135,14 @@ enum PrepKind : int32_t {
   PREP_COEF1 = 4,   // Pauli coefficients (hx, hy, hz) of V G_k V^dag for factor k
   PREP_COEF2 = 5,   // U2 generator scale (c of G = c P(x)P)
   PREP_COEFD = 6,   // diag term class-sum coefficients (P_0, P_a[, P_b, P_ab])
-  PREP_MATD = 7,    // dense layer matrix factor (unused placeholder)
+  PREP_DENSE = 8,   // full layer matrix (2^nv x 2^nv, dtype) from the layer's gates; one thread per column
 };
 
 struct Factor {
   int32_t gate;     // tqs_gate
   int32_t src;      // tqs_source
   int32_t pidx;     // weight / feature index
-  int32_t pad;
+  int32_t wires;    // dense layers: state bit of the first wire | (state bit of the second + 1) << 8
   double fixed;
 };
 

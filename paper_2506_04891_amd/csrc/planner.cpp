@@ -31,6 +31,11 @@
 
 namespace tqs {
 
+// Dense (full layer unitary) dispatch: allowed up to this many qubits; chosen
+// automatically up to DENSE_AUTO_MAX_QUBITS.
+constexpr int DENSE_MAX_QUBITS = 6;
+constexpr int DENSE_AUTO_MAX_QUBITS = 0;
+
 // gate ids (tqs_gate)
 enum { RX = 0, RY, RZ, H, X, Z, S, SX, GPI, GPI2, CNOT, CZ, SWAP, ZZ, MS, ECR, GPI_DIAG = 100 };
 enum { PAT_ALL = 0, PAT_WIRE, PAT_RING, PAT_CHAIN, PAT_PEVEN, PAT_PODD };
@@ -235,7 +240,7 @@ struct Builder {
     f.gate = gate_override >= 0 ? gate_override : in.gate;
     f.src = in.src;
     f.pidx = in.pidx;
-    f.pad = 0;
+    f.wires = 0;
     f.fixed = in.fixed;
     P.factors.push_back(f);
     return (int)P.factors.size() - 1;
@@ -273,7 +278,9 @@ static void finish_op(Plan &P, IrOp &op) {
   op.mask = 0;
   if (op.kind == IR_U1) op.mask = 1u << op.bits[0];
   if (op.kind == IR_U2) op.mask = (1u << op.bits[0]) | (1u << op.bits[1]);
-  if (op.kind == IR_PERM) op.mask = (P.n >= 32) ? 0xffffffffu : ((1u << P.n) - 1u);
+  if (op.kind == IR_PERM || op.kind == IR_DENSE) op.mask = (P.n >= 32) ? 0xffffffffu : ((1u << P.n) - 1u);
+  if (op.kind == IR_GRAD1) op.mask = 1u << op.bits[0];
+  if (op.kind == IR_GRAD2) op.mask = (1u << op.bits[0]) | (1u << op.bits[1]);
   std::vector<int> fs = op.factors;
   for (const IrTerm &t : op.terms) {
     fs.push_back(t.factor);
@@ -296,6 +303,7 @@ static void finish_op(Plan &P, IrOp &op) {
     op.real = is_real_gate(g);
     op.diagonal = is_diag2(g);
   }
+  if (op.kind == IR_DENSE) op.has_grad = false;
 }
 
 static std::string build_ir(Plan &P, const std::vector<Inst> &insts) {
@@ -326,6 +334,41 @@ static std::string build_ir(Plan &P, const std::vector<Inst> &insts) {
   int cur_layer = -1, layer_diag = -1, layer_perm = -1, gpi_diag = -1, gpi_perm = -1;
   for (size_t i = 0; i < insts.size(); ++i) {
     if (consumed[i]) continue;
+    if (P.dense) {
+      // a layer without per-sample parameters becomes one full-unitary op
+      // (the paper's unitary operation, Sec. 2.2.1) plus gradient-only sums
+      std::vector<size_t> mem;
+      bool input = false;
+      for (size_t j = i; j < insts.size() && insts[j].layer == insts[i].layer; ++j)
+        if (!consumed[j]) {
+          mem.push_back(j);
+          if (insts[j].src == SRC_INPUT) input = true;
+        }
+      if (!input) {
+        const int od = B.new_op(IR_DENSE);
+        std::vector<IrOp> grads;
+        for (size_t j : mem) {
+          const Inst &q = insts[j];
+          const int f = B.add_factor(q);
+          P.factors[f].wires = B.bit(q.w0) | ((q.w1 >= 0 ? B.bit(q.w1) + 1 : 0) << 8);
+          P.ops[od].factors.push_back(f);
+          if (is_param(q.gate) && q.src != SRC_FIXED) {
+            IrOp g;
+            g.kind = is_1q(q.gate) ? IR_GRAD1 : IR_GRAD2;
+            g.bits[0] = B.bit(q.w0);
+            g.bits[1] = q.w1 >= 0 ? B.bit(q.w1) : -1;
+            g.factors.push_back(f);
+            grads.push_back(g);
+          }
+          consumed[j] = 1;
+        }
+        for (auto &g : grads) P.ops.push_back(g);
+        for (int w = 0; w < n; ++w) open_u1[w] = -1;
+        layer_diag = layer_perm = gpi_diag = gpi_perm = -1;
+        cur_layer = insts[i].layer;
+        continue;
+      }
+    }
     const Inst &in = insts[i];
     if (in.layer != cur_layer) {
       cur_layer = in.layer;
@@ -773,6 +816,11 @@ static std::string emit(Plan &P) {
       op_mat[i] = E.alloc_mat(op.per_sample, 16);
       op_ps[i] = op.per_sample;
       E.prep(PREP_MAT2, op.per_sample, op_mat[i], sl, sl + 1, 0);
+    } else if (op.kind == IR_DENSE) {
+      const int dim = 1 << P.nv;
+      const int sl = E.factors_slice(op.factors);
+      op_mat[i] = E.alloc_mat(false, dim * dim);
+      E.prep(PREP_DENSE, false, op_mat[i], sl, sl + (int)op.factors.size(), 0);
     } else if (op.kind == IR_DIAG) {
       for (const IrTerm &t : op.terms) {
         const bool ps = P.factors[t.factor].src == SRC_INPUT;
@@ -876,6 +924,7 @@ static std::string emit(Plan &P) {
       d.store_c = pp.store_map.c;
     }
     d.load_mode = pp.load_mode;
+    d.dense_off = -1;
     d.embed_mat = embed_mat;
     d.embed_per_sample = P.embed_per_sample;
     d.diag_begin = (int)P.ddiag.size();
@@ -895,8 +944,8 @@ static std::string emit(Plan &P) {
     std::vector<int> diag_index(P.ops.size(), -1);
     auto tile_bits_of = [&](const IrOp &op) {
       std::vector<int> v;
-      if (op.kind == IR_U1) v.push_back(tix.at(op.bits[0]));
-      if (op.kind == IR_U2) {
+      if (op.kind == IR_U1 || op.kind == IR_GRAD1) v.push_back(tix.at(op.bits[0]));
+      if (op.kind == IR_U2 || op.kind == IR_GRAD2) {
         v.push_back(tix.at(op.bits[0]));
         v.push_back(tix.at(op.bits[1]));
       }
@@ -1016,6 +1065,34 @@ static std::string emit(Plan &P) {
         }
         o.aux = diag_index[oi_ir];
         o.flags = op.has_grad ? F_GRAD : 0;
+      } else if (op.kind == IR_DENSE) {
+        o.kind = OP_DENSE;
+        o.mat = op_mat[oi_ir];
+        if (d.dense_off < 0) {
+          d.dense_off = d.diag_lds;
+          d.diag_lds += 1 << K;
+        }
+      } else if (op.kind == IR_GRAD1) {
+        o.kind = OP_GRAD1;
+        o.r0 = ridx(tix.at(op.bits[0]));
+        o.flags = F_GRAD;
+        o.mat = 0;
+        o.acc = n_acc;
+        E.u1_contribs(op.factors, P.n_acc + n_acc);
+        n_acc += 3;
+      } else if (op.kind == IR_GRAD2) {
+        const Factor &f = P.factors[op.factors[0]];
+        o.kind = OP_GRAD2;
+        o.r0 = ridx(tix.at(op.bits[0]));
+        o.r1 = ridx(tix.at(op.bits[1]));
+        o.flags = F_GRAD;
+        o.acc = n_acc;
+        o.aux = (f.gate == MS) ? (1 | (1 << 2)) : (3 | (3 << 2));
+        const int co = E.alloc_dbl(false, 1);
+        const int sl = E.factors_slice(op.factors);
+        E.prep(PREP_COEF2, false, co, sl, sl + 1, sl);
+        E.contrib(f, P.n_acc + n_acc, 1, co, false);
+        n_acc += 1;
       } else if (op.kind == IR_PERM) {
         o.kind = OP_PERM;
         DevPerm pm;
@@ -1046,7 +1123,7 @@ static std::string emit(Plan &P) {
             if (!done[i]) ready = false;
           if (!ready) continue;
           const IrOp &op = P.ops[po[j]];
-          if (op.kind == IR_PERM) {
+          if (op.kind == IR_PERM || op.kind == IR_DENSE) {
             if (stage_ops.empty()) {
               stage_ops.push_back((int)j);
               done[j] = 1;
@@ -1188,13 +1265,17 @@ std::string build_plan(Plan &P, int n, const LayerSpec *layers, int n_layers, in
   P.nv = std::max(n, RB);
   P.dtype = dtype;
   P.mode = mode == 0 ? 2 : mode;
-  if (P.mode == 3) P.mode = 2;   // dense requests fall back to the fused tile engine here
+  const bool want_dense = (P.mode == 3) || (mode == 0 && n <= DENSE_AUTO_MAX_QUBITS);
+  if (P.mode == 3) P.mode = 2;
   P.tile_bits = tile_bits;
   const int kdef = dtype == 0 ? 12 : 11;
   int K = tile_bits ? tile_bits : kdef;
   if (dtype == 1 && K > 11) K = 11;
   P.resident = P.nv <= K;
   if (P.resident) K = std::max(P.nv, KMIN);
+  // full layer unitaries need the whole state of a sample in the tile and at
+  // least 16 samples per workgroup (one MFMA column block)
+  P.dense = want_dense && P.resident && P.nv <= DENSE_MAX_QUBITS && K - P.nv >= 4;
   P.factors.clear();
   P.ops.clear();
   std::vector<Inst> insts = expand(n, layers, n_layers);
@@ -1215,13 +1296,13 @@ std::string build_plan(Plan &P, int n, const LayerSpec *layers, int n_layers, in
 std::string describe_plan(const Plan &P) {
   std::ostringstream o;
   o << "{\"n\":" << P.n << ",\"dtype\":\"" << (P.dtype ? "c128" : "c64") << "\",\"mode\":\""
-    << (P.mode == 1 ? "per_layer" : "fused") << "\",\"resident\":" << (P.resident ? "true" : "false")
+    << (P.dense ? "dense" : (P.mode == 1 ? "per_layer" : "fused")) << "\",\"resident\":" << (P.resident ? "true" : "false")
     << ",\"n_weights\":" << P.n_weights << ",\"n_features\":" << P.n_features << ",\"n_ops\":" << P.ops.size()
     << ",\"n_acc\":" << P.n_acc << ",\"passes\":[";
   for (size_t p = 0; p < P.passes.size(); ++p) {
     const PlanPass &pp = P.passes[p];
     const DevPass &d = P.dpass[p];
-    int nu1 = 0, nu2 = 0, ndg = 0, npm = 0;
+    int nu1 = 0, nu2 = 0, ndg = 0, npm = 0, ndense = 0;
     for (int s = d.stage_begin; s < d.stage_begin + d.n_stages; ++s)
       for (int oi = P.dstage[s].op_begin; oi < P.dstage[s].op_end; ++oi) {
         const int k = P.dop[oi].kind;
@@ -1229,13 +1310,15 @@ std::string describe_plan(const Plan &P) {
         nu2 += k == OP_U2;
         ndg += k == OP_DIAG;
         npm += k == OP_PERM;
+        ndense += k == OP_DENSE;
       }
     o << (p ? "," : "") << "{\"K\":" << pp.K << ",\"tile\":[";
     for (size_t t = 0; t < pp.tile.size(); ++t) o << (t ? "," : "") << pp.tile[t];
     o << "],\"load\":\"" << (pp.load_mode == LOAD_EMBED ? "embed" : (pp.has_load ? "gather" : "tile"))
       << "\",\"store\":\"" << (pp.has_store ? "scatter" : "tile") << "\",\"bwd_only\":"
       << (pp.bwd_only ? "true" : "false") << ",\"stages\":" << d.n_stages << ",\"u1\":" << nu1
-      << ",\"u2\":" << nu2 << ",\"diag\":" << ndg << ",\"perm\":" << npm << ",\"grad_wires\":"
+      << ",\"u2\":" << nu2 << ",\"diag\":" << ndg << ",\"perm\":" << npm << ",\"dense\":" << ndense
+      << ",\"grad_wires\":"
       << pp.grad_wires.size() << ",\"n_acc\":" << d.n_acc << "}";
   }
   o << "]}";

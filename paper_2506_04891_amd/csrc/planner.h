@@ -21,7 +21,7 @@ struct GF2 {
   bool is_identity() const;
 };
 
-enum IrKind { IR_U1 = 1, IR_U2 = 2, IR_DIAG = 3, IR_PERM = 4 };
+enum IrKind { IR_U1 = 1, IR_U2 = 2, IR_DIAG = 3, IR_PERM = 4, IR_DENSE = 5, IR_GRAD1 = 6, IR_GRAD2 = 7 };
 
 struct IrTerm {
   int factor;
@@ -55,6 +55,7 @@ struct PlanPass {
 struct Plan {
   // configuration
   int n = 0, nv = 0, dtype = 0, mode = 0, tile_bits = 0;
+  bool dense = false;                    // weight-only layers applied as full unitaries (MFMA)
   int n_weights = 0, n_features = 0;
   bool resident = false;
   // IR

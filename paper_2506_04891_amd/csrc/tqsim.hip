@@ -255,6 +255,9 @@ double op_flops(const DevOp &o) {
   }
 }
 
+// Dense op: 2^nv complex multiply-adds per amplitude.
+double dense_flops(int nv) { return 8.0 * (double)(1 << nv); }
+
 // Backward flops of an op per amplitude: psi and lambda are both uncomputed
 // (2x forward) and ops with parameters add their gradient sums (U1: three
 // Pauli sums over pairs, 6 flops per amplitude each; U2 / diagonal: one sum).
@@ -308,8 +311,12 @@ tqs_status launch_pass(tqs_circuit *c, int pi, int B, const cplx<T> *src0, cplx<
       bytes = amps * es * ((d.load_mode == LOAD_GLOBAL ? 1.0 : 0.0) + 1.0);
     double f = 0;
     for (int st = d.stage_begin; st < d.stage_begin + d.n_stages; ++st)
-      for (int oi = P.dstage[st].op_begin; oi < P.dstage[st].op_end; ++oi)
-        f += BWD ? op_flops_bwd(P.dop[oi]) : op_flops(P.dop[oi]);
+      for (int oi = P.dstage[st].op_begin; oi < P.dstage[st].op_end; ++oi) {
+        if (P.dop[oi].kind == OP_DENSE)
+          f += (BWD ? 2.0 : 1.0) * dense_flops(P.nv);
+        else
+          f += BWD ? op_flops_bwd(P.dop[oi]) : op_flops(P.dop[oi]);
+      }
     if (BWD)
       for (int st = d.grad_stage_begin; st < d.grad_stage_begin + d.n_grad_stages; ++st)
         f += 18.0 * (P.dstage[st].op_end - P.dstage[st].op_begin);
@@ -347,6 +354,7 @@ tqs_status do_prep(tqs_circuit *c, int B, const double *w, const double *x, char
   a.dbl = reinterpret_cast<double *>(ws + L.dbl);
   a.dbl_ps = reinterpret_cast<double *>(ws + L.dbl_ps);
   a.dbl_ps_stride = P.n_dbl_ps;
+  a.nv = P.nv;
   dim3 grid((B + 63) / 64, (unsigned)P.prep.size());
   ProfScope ps(c, s, "prep", 0.0, 0.0);
   hipLaunchKernelGGL((k_prep<T>), grid, dim3(64), 0, s, a);

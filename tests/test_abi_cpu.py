@@ -117,3 +117,23 @@ def test_plans_cover_every_op(mode, n):
     fw = [q for q in p["passes"] if not q["bwd_only"]]
     assert fw[0]["load"] == "embed"
     assert sum(q["u1"] + q["u2"] + q["diag"] + q["perm"] for q in fw) >= 1 or n == 1
+
+
+@pytest.mark.parametrize("n", [1, 3, 4, 6, 7, 10])
+def test_dense_mode_plans(n):
+    """Dense mode puts every weight-only layer into one full-unitary op for
+    n <= 6 (input-driven layers keep their own kernels); above 6 qubits it
+    falls back to the per-layer tile pass."""
+    T = _lib()
+    layers = W.circuit_rot_ring(n, 2, "RX", ("RX", "RY", "RZ"), zz=True)
+    c = T.Circuit(n, layers, "c64", mode="dense")
+    p = c.plan()
+    if n <= 6:
+        assert p["mode"] == "dense" and len(p["passes"]) == 1
+        # 2 blocks x (RX, RY, RZ, ZZ ring, CNOT ring) weight-only layers; the
+        # first block's rotations fold into the product-state embedding, and at
+        # one qubit (no rings) everything does
+        assert p["passes"][0]["dense"] == (7 if n > 1 else 0)
+    else:
+        assert p["mode"] != "dense"
+        assert all(q["dense"] == 0 for q in p["passes"])

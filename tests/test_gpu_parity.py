@@ -80,6 +80,61 @@ def test_layer_kind_c128(spec, n, mode):
     compare(got, ref, "c128", label=f"{spec} n={n} {mode}")
 
 
+@pytest.mark.parametrize("n", [1, 2, 3, 4, 5, 6])
+@pytest.mark.parametrize("spec", LAYER_KINDS, ids=["-".join(s) for s in LAYER_KINDS])
+def test_layer_kind_dense_c64(spec, n):
+    """Full-unitary layers on the matrix cores (n <= 6), single precision."""
+    if "PAIRS" in spec[1] and n % 2:
+        pytest.skip("brick pairs need even n")
+    layers = _sandwich(n, spec)
+    B = 5
+    w, x, g = _params(n, layers, B, seed=200 + n)
+    note(f"case layer={spec} n={n} mode=dense c64")
+    c = _circuit(n, layers, "c64", "dense")
+    assert c.plan()["mode"] == "dense"
+    got = gpu_run(c, w, x, g)
+    ref = oracle_run(n, layers, w, x, g)
+    compare(got, ref, "c64", label=f"{spec} n={n} dense")
+
+
+@pytest.mark.parametrize("n", [2, 4, 6])
+@pytest.mark.parametrize("spec", LAYER_KINDS, ids=["-".join(s) for s in LAYER_KINDS])
+def test_layer_kind_dense_c128(spec, n):
+    """Full-unitary layers on the FP64 matrix cores, double precision."""
+    layers = _sandwich(n, spec)
+    B = 3
+    w, x, g = _params(n, layers, B, seed=300 + n)
+    note(f"case layer={spec} n={n} mode=dense c128")
+    got = gpu_run(_circuit(n, layers, "c128", "dense"), w, x, g)
+    ref = oracle_run(n, layers, w, x, g)
+    compare(got, ref, "c128", label=f"{spec} n={n} dense")
+
+
+@pytest.mark.parametrize("B", [1, 17, 65])
+@pytest.mark.parametrize("name,n,builder,dist", [
+    ("ionq", 6, lambda n: W.circuit_ionq(n, 4), "uniform2pi"),
+    ("ibm", 6, lambda n: W.circuit_ibm(n, 4), "uniform2pi"),
+    ("rot_ring_zz", 5, lambda n: W.circuit_rot_ring(n, 3, "RX", ("RX", "RY", "RZ"), zz=True), "normal"),
+])
+def test_dense_circuits(name, n, builder, dist, B):
+    """Whole native-gate circuits in dense mode, ragged sample groups."""
+    layers = builder(n)
+    w, x, g = _params(n, layers, B, seed=B, dist=dist)
+    note(f"case dense {name} n={n} B={B}")
+    got = gpu_run(_circuit(n, layers, "c64", "dense"), w, x, g)
+    ref = oracle_run(n, layers, w, x, g)
+    compare(got, ref, "c64", label=f"dense {name} n={n} B={B}")
+
+
+def test_config1_dense_exact():
+    n, B, dt, layers, w, x = W.config("c1_4q_b16")
+    g = W.upstream(B, n, "normal", 1)
+    note("case c1 mode=dense")
+    got = gpu_run(_circuit(n, layers, dt, "dense"), w, x, g)
+    ref = oracle_run(n, layers, w, x, g)
+    compare(got, ref, "c128", label="c1 dense")
+
+
 @pytest.mark.parametrize("tile_bits", [10, 11, 12])
 @pytest.mark.parametrize("name,builder,dist", [
     ("rot_ring_zz", lambda n: W.circuit_rot_ring(n, 3, "RX", ("RX", "RY", "RZ"), zz=True), "normal"),
