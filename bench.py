@@ -36,15 +36,28 @@ def parse():
     p.add_argument("--mode", default="auto", choices=["auto", "per_layer", "fused"])
     p.add_argument("--no-serve", action="store_true")
     p.add_argument("--serve-requests", type=int, default=160)
-    p.add_argument("--serve-max-qubits", type=int, default=16)
+    p.add_argument("--serve-max-qubits", type=int, default=22)
     p.add_argument("--serve-qps-fracs", default="0.5,0.8,0.95")
+    p.add_argument("--no-b512", action="store_true")
+    # after the timed region, run a plain streaming kernel (float32 negation)
+    # over this many MiB three times: the known-size reference that scales
+    # rocprofv3's FETCH_SIZE / WRITE_SIZE readings to bytes
+    p.add_argument("--calibrate-copy-mib", type=int, default=0)
     return p.parse_args()
 
 
-def roofline(report, traffic=None):
-    """Roofline object of the kernel kind with the largest total time."""
+def traffic_file(kind):
+    return os.path.join(ROOT, "profiles", f"traffic_{kind}_16q_b128.txt")
+
+
+def roofline(report, traffic_path=None):
+    """Roofline object of the kernel kind with the largest total time.
+    `traffic` is the counter-measured HBM bytes per launch of that kernel,
+    from the summary at `traffic_path` when it was taken on these sources."""
+    from paper_2506_04891_amd.rocprof_summary import read_traffic
     kinds = {k: v for k, v in report.items() if v["count"] > 0}
     name = max(kinds, key=lambda k: kinds[k]["ms"])
+    traffic = read_traffic(traffic_path(name), name) if traffic_path else None
     r = kinds[name]
     sec = r["ms"] / 1e3
     intensity = r["flops"] / max(r["bytes"], 1.0)
@@ -67,11 +80,15 @@ def roofline(report, traffic=None):
 class Job:
     """One circuit at its full batch, device tensors resident in HBM."""
 
-    def __init__(self, name, mode):
+    def __init__(self, name, mode, batch=None):
         import torch
         import workloads as W
         from paper_2506_04891_amd import tqsim as T
         n, B, dt, layers, w, x = W.config(name)
+        if batch is not None:
+            cfg = W.CONFIGS[name]
+            B = batch
+            w, x = W.draw_params(n, layers, B, cfg["wdist"], cfg["seed"])
         self.name, self.n, self.B = name, n, B
         self.circ = T.Circuit(n, layers, dt, mode=mode)
         dev = torch.device("cuda")
@@ -229,9 +246,24 @@ def main():
                                "native-gate circuits, 8 blocks each, forward <Z_i> + adjoint gradients",
                    "n_qubits": 16, "batch": 128, "circuits": [j.name for j in jobs],
                    "mode": a.mode, "passes": {j.name: len(j.circ.plan()["passes"]) for j in jobs}},
-        "roofline": roofline(rep),
+        "roofline": roofline(rep, traffic_file),
         "kernels": {k: {"count": v["count"], "ms_per_step": round(v["ms"] / a.steps, 4)} for k, v in rep.items()},
     }
+    if a.calibrate_copy_mib > 0:
+        src = torch.ones(a.calibrate_copy_mib << 18, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            torch.neg(src, out=dst)
+        torch.cuda.synchronize()
+        del src, dst
+    if not a.no_b512:
+        jb = [Job("c4a_16q_b128_ionq", a.mode, 512), Job("c4b_16q_b128_ibm", a.mode, 512)]
+        msb, _, repb = time_jobs(jb, max(3, a.steps // 4), 2)
+        out["q16_b512"] = {"workload": "the same two 16-qubit circuits at batch 512 (256 MiB per state set, "
+                                       "larger than the last-level cache)",
+                           "evals_per_s": round(1024 / (msb / 1e3), 1), "ms_per_step": round(msb, 3),
+                           "roofline": roofline(repb)}
+        del jb
     if not a.no_20q:
         j20 = Job("c3_20q_b32", a.mode)
         ms20, _, rep20 = time_jobs([j20], max(3, a.steps // 4), 2)

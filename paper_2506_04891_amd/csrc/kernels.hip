@@ -339,11 +339,7 @@ __global__ void __launch_bounds__(64) k_prep(PrepArgs<T> a) {
   const int b = blockIdx.x * 64 + threadIdx.x;
   if (item >= a.n_items) return;
   const PrepItem it = ld_item(a.items + item);
-  if (it.kind == PREP_DENSE) {
-    if (b >= (1 << a.nv)) return;   // one thread per matrix column
-  } else if (it.per_sample ? (b >= a.batch) : (b != 0)) {
-    return;
-  }
+  if (it.per_sample ? (b >= a.batch) : (b != 0)) return;
   const int bs = it.per_sample ? b : 0;
   switch (it.kind) {
     case PREP_MAT1: {
@@ -415,45 +411,59 @@ __global__ void __launch_bounds__(64) k_prep(PrepArgs<T> a) {
       o[0] = c;
       break;
     }
-    case PREP_DENSE: {
-      // column `b` of the layer's full matrix: apply the layer's gates, in
-      // order, to the basis vector e_b (FP64), write U[:, b] rounded to dtype
-      const int dim = 1 << a.nv;
-      zd v[64];
-      for (int j = 0; j < dim; ++j) v[j] = zmk(j == b ? 1.0 : 0.0, 0.0);
-      for (int k = it.f_begin; k < it.f_end; ++k) {
-        const Factor fc = ld_factor(a.factors + k);
-        const double th = factor_param(fc, a.w, a.x, a.nfeat, 0);
-        const int p0 = fc.wires & 0xff, p1 = (fc.wires >> 8) - 1;
-        if (p1 < 0) {
-          zd m[4], d[4];
-          gate2(fc.gate, th, m, d);
-          for (int j = 0; j < dim; ++j) {
-            if ((j >> p0) & 1) continue;
-            const zd x0 = v[j], x1 = v[j | (1 << p0)];
-            v[j] = zadd(zmul(m[0], x0), zmul(m[1], x1));
-            v[j | (1 << p0)] = zadd(zmul(m[2], x0), zmul(m[3], x1));
-          }
-        } else {
-          zd m[16];
-          gate4(fc.gate, th, m);
-          for (int j = 0; j < dim; ++j) {
-            if (((j >> p0) & 1) || ((j >> p1) & 1)) continue;
-            const int q[4] = {j, j | (1 << p1), j | (1 << p0), j | (1 << p0) | (1 << p1)};
-            zd x[4] = {v[q[0]], v[q[1]], v[q[2]], v[q[3]]};
-            for (int r = 0; r < 4; ++r) {
-              zd acc = zmk(0, 0);
-              for (int cc = 0; cc < 4; ++cc) acc = zadd(acc, zmul(m[r * 4 + cc], x[cc]));
-              v[q[r]] = acc;
-            }
-          }
-        }
-      }
-      cplx<T> *o = a.mats + it.out;
-      for (int j = 0; j < dim; ++j) o[(long long)j * dim + b] = cmk<T>((T)v[j].x, (T)v[j].y);
-      break;
+    case PREP_DENSE:
+      break;   // built by k_prep_dense
+  }
+}
+
+// Full matrix of a dense layer (up to 64 x 64): one wave per column c.  Lane j
+// holds amplitude j of U e_c in FP64; each gate of the layer, in order, mixes
+// a lane with its partners across the gate's bits (lane shuffles), and the
+// column is written rounded to the state dtype.
+__device__ __forceinline__ zd shfl_xor_zd(zd v, int m) {
+  zd r;
+  r.x = __shfl_xor(v.x, m, 64);
+  r.y = __shfl_xor(v.y, m, 64);
+  return r;
+}
+
+template <typename T>
+__global__ void __launch_bounds__(64) k_prep_dense(PrepArgs<T> a) {
+  const int item = blockIdx.y;
+  const int col = blockIdx.x;
+  const int j = threadIdx.x;
+  const int dim = 1 << a.nv;
+  if (item >= a.n_items || col >= dim) return;
+  const PrepItem it = ld_item(a.items + item);
+  if (it.kind != PREP_DENSE) return;
+  zd v = zmk(j == col ? 1.0 : 0.0, 0.0);
+  for (int k = it.f_begin; k < it.f_end; ++k) {
+    const Factor fc = ld_factor(a.factors + k);
+    const double th = factor_param(fc, a.w, a.x, a.nfeat, 0);
+    const int p0 = fc.wires & 0xff, p1 = (fc.wires >> 8) - 1;
+    if (p1 < 0) {
+      zd m[4], d[4];
+      gate2(fc.gate, th, m, d);
+      const int b0 = (j >> p0) & 1;
+      const zd o = shfl_xor_zd(v, 1 << p0);
+      // row b0 of the 2x2: own amplitude sits in column b0, partner in 1-b0
+      v = zadd(zmul(m[b0 * 3], v), zmul(m[b0 ? 2 : 1], o));
+    } else {
+      zd m[16];
+      gate4(fc.gate, th, m);
+      const int m0 = 1 << p0, m1 = 1 << p1;
+      const zd x1 = shfl_xor_zd(v, m1), x2 = shfl_xor_zd(v, m0), x3 = shfl_xor_zd(v, m0 | m1);
+      const int r = 2 * ((j >> p0) & 1) + ((j >> p1) & 1);
+      // partner at xor-mask q holds the amplitude of row index r ^ q'
+      // (q' = 1 for the second wire, 2 for the first)
+      zd acc = zmul(m[r * 4 + r], v);
+      acc = zadd(acc, zmul(m[r * 4 + (r ^ 1)], x1));
+      acc = zadd(acc, zmul(m[r * 4 + (r ^ 2)], x2));
+      acc = zadd(acc, zmul(m[r * 4 + (r ^ 3)], x3));
+      v = acc;
     }
   }
+  if (j < dim) a.mats[it.out + (long long)j * dim + col] = cmk<T>((T)v.x, (T)v.y);
 }
 
 // ---------------------------------------------------------------------------
@@ -994,12 +1004,12 @@ __device__ __forceinline__ void dense_apply(const Ctx<T, K> &c, cplx<T> *X, cplx
   __syncthreads();
 }
 
-template <typename T, int K, bool BWD>
+template <typename T, int K, bool BWD, bool DENSE>
 __device__ __forceinline__ void run_stage(const Ctx<T, K> &c, const PassArgs<T> &a, const UStage &S, cplx<T> *Lp,
                           cplx<T> *Ll, const cplx<T> *tab, bool grad_only) {
   constexpr int NT = Ctx<T, K>::NT;
   const int op0_kind = uni(a.ops[S.op_begin].kind);
-  if (op0_kind == OP_DENSE) {
+  if (DENSE && op0_kind == OP_DENSE) {
     kptr<cplx<T>> U = a.mats + uni(a.ops[S.op_begin].mat);
     cplx<T> *scr = const_cast<cplx<T> *>(tab) + uni(a.pass->dense_off);
     __syncthreads();
@@ -1104,7 +1114,7 @@ __device__ __forceinline__ void run_stage(const Ctx<T, K> &c, const PassArgs<T> 
       }
       u2_apply_any<T, BWD>(vp, mg, op.r0, op.r1, op.sub);
       if (BWD) u2_apply_any<T, true>(vl, mg, op.r0, op.r1, op.sub);
-    } else if (op.kind == OP_GRAD2) {
+    } else if (DENSE && op.kind == OP_GRAD2) {
       if (BWD && (op.flags & F_GRAD)) {
         const T g = (op.aux == (1 | (1 << 2))) ? u2s_grad_dispatch<T, true>(vp, vl, op.r0, op.r1)
                                                 : u2s_grad_dispatch<T, false>(vp, vl, op.r0, op.r1);
@@ -1165,7 +1175,7 @@ __device__ __forceinline__ void run_stage(const Ctx<T, K> &c, const PassArgs<T> 
   __syncthreads();
 }
 
-template <typename T, int K, bool BWD>
+template <typename T, int K, bool BWD, bool DENSE>
 __global__ void __launch_bounds__(1 << (K - RB)) k_pass(PassArgs<T> a) {
   constexpr int NT = 1 << (K - RB);
   constexpr int NE = 1 << K;
@@ -1340,13 +1350,13 @@ __global__ void __launch_bounds__(1 << (K - RB)) k_pass(PassArgs<T> a) {
   const int ns = uni(P->n_stages), sb = uni(P->stage_begin);
   for (int si = 0; si < ns; ++si) {
     const UStage S = load_stage(a.stages + sb + (BWD ? (ns - 1 - si) : si));
-    run_stage<T, K, BWD>(c, a, S, Lp, Ll, tab, false);
+    run_stage<T, K, BWD, DENSE>(c, a, S, Lp, Ll, tab, false);
   }
   if (BWD) {
     const int ng = uni(P->n_grad_stages), gsb = uni(P->grad_stage_begin);
     for (int si = 0; si < ng; ++si) {
       const UStage S = load_stage(a.stages + gsb + si);
-      run_stage<T, K, BWD>(c, a, S, Lp, Ll, tab, true);
+      run_stage<T, K, BWD, DENSE>(c, a, S, Lp, Ll, tab, true);
     }
     if (uni(P->skip_bwd_store)) return;
   }
@@ -1515,26 +1525,32 @@ __global__ void __launch_bounds__(NTE) k_expval(ReadArgs<T> a) {
 // Sum of a double across the 64 lanes of a wave, in a fixed order; valid in lane 63.
 __device__ __forceinline__ double wave_sum(double v) { return seg_sum_dpp(v, 6); }
 
+constexpr int NTR = 256;   // threads per block of the grouped reduction kernels
+
 // expz[b, i] and norm[b] from the partials; wire i <-> state bit p = n-1-i.
-// One wave per output (b, i); i == n gives the norm.
-__global__ void __launch_bounds__(64) k_expval_final(const double *partials, double *expz, double *norm, int n,
-                                                     int batch) {
-  const int b = blockIdx.x / (n + 1), i = blockIdx.x % (n + 1);
-  const int lane = threadIdx.x;
-  const long long units = n > KE ? (1ll << (n - KE)) : 1;
-  const int p = n - 1 - i;
+// A group of 2^gl lanes per output (b, i); i == n gives the norm.
+__global__ void __launch_bounds__(NTR) k_expval_final(const double *partials, double *expz, double *norm, int n,
+                                                      int batch, int gl) {
+  const long long o = ((long long)blockIdx.x * NTR + threadIdx.x) >> gl;
+  const int g = threadIdx.x & ((1 << gl) - 1);
+  const bool valid = o < (long long)batch * (n + 1);
   double s = 0.0;
-  for (long long u = lane; u < units; u += 64) {
-    const double *q = partials + ((long long)b * units + u) * (KE + 1);
-    if (i == n)
-      s += q[0];
-    else if (p < KE)
-      s += q[1 + p];
-    else
-      s += ((u >> (p - KE)) & 1) ? -q[0] : q[0];
+  const int b = (int)(o / (n + 1)), i = (int)(o % (n + 1));
+  if (valid) {
+    const long long units = n > KE ? (1ll << (n - KE)) : 1;
+    const int p = n - 1 - i;
+    for (long long u = g; u < units; u += (1 << gl)) {
+      const double *q = partials + ((long long)b * units + u) * (KE + 1);
+      if (i == n)
+        s += q[0];
+      else if (p < KE)
+        s += q[1 + p];
+      else
+        s += ((u >> (p - KE)) & 1) ? -q[0] : q[0];
+    }
   }
-  s = wave_sum(s);
-  if (lane == 63) {
+  s = seg_sum_dpp(s, gl);
+  if (valid && g == (1 << gl) - 1) {
     if (i == n) {
       if (norm) norm[b] = s;
     } else {
@@ -1578,38 +1594,56 @@ __global__ void __launch_bounds__(NTE) k_adj_init(ReadArgs<T> a) {
 }
 
 // A[acc][b] = sum of the pass partials of sample b (FP64, fixed order); one wave per (acc, b).
+// Deterministic grouped reductions: 2^gl lanes per output (gl chosen on the
+// host from the longest sum), each lane summing a fixed stride of the terms in
+// order, then a fixed DPP tree within the group.  Blocks of NTR threads.
+
 template <typename T>
-__global__ void __launch_bounds__(64) k_acc_reduce(const T *partials, const long long *acc_static,
-                                                   const int *acc_units, int n_acc, int batch, double *A) {
-  const long long idx = blockIdx.x;
-  const int acc = (int)(idx / batch), b = (int)(idx % batch);
-  const int U = acc_units[acc];
-  const T *p = partials + acc_static[acc] * batch + (long long)b * U;
+__global__ void __launch_bounds__(NTR) k_acc_reduce(const T *partials, const long long *acc_static,
+                                                    const int *acc_units, int n_acc, int batch, double *A,
+                                                    int gl) {
+  const long long o = ((long long)blockIdx.x * NTR + threadIdx.x) >> gl;
+  const int g = threadIdx.x & ((1 << gl) - 1);
+  const bool valid = o < (long long)n_acc * batch;
   double s = 0.0;
-  for (int u = threadIdx.x; u < U; u += 64) s += (double)p[u];
-  s = wave_sum(s);
-  if (threadIdx.x == 63) A[idx] = s;
+  if (valid) {
+    const int acc = (int)(o / batch), b = (int)(o % batch);
+    const int U = acc_units[acc];
+    const T *p = partials + acc_static[acc] * batch + (long long)b * U;
+    for (int u = g; u < U; u += (1 << gl)) s += (double)p[u];
+  }
+  s = seg_sum_dpp(s, gl);
+  if (valid && g == (1 << gl) - 1) A[o] = s;
 }
 
-// gradients: weights sum over samples; features per sample
-__global__ void k_grad_combine(const int *cptr, const Contrib *contribs, const double *A,
-                               const double *dbl, const double *dbl_ps, int dbl_ps_stride, int n_w,
-                               int n_x, int batch, double *gw, double *gx) {
-  const long long idx = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (idx < n_w) {
-    const int p = (int)idx;
-    double s = 0.0;
-    for (int b = 0; b < batch; ++b)
+// weight gradients: sum over samples of the accumulator combinations; one
+// group of 2^gl lanes per weight, lanes striding over the batch
+__global__ void __launch_bounds__(NTR) k_grad_weights(const int *cptr, const Contrib *contribs, const double *A,
+                                                      const double *dbl, const double *dbl_ps, int dbl_ps_stride,
+                                                      int n_w, int batch, double *gw, int gl) {
+  const long long o = ((long long)blockIdx.x * NTR + threadIdx.x) >> gl;
+  const int g = threadIdx.x & ((1 << gl) - 1);
+  const bool valid = o < n_w;
+  double s = 0.0;
+  if (valid) {
+    const int p = (int)o;
+    for (int b = g; b < batch; b += (1 << gl))
       for (int ci = cptr[p]; ci < cptr[p + 1]; ++ci) {
         const Contrib cb = contribs[ci];
         const double *co = cb.coef_ps ? dbl_ps + (size_t)b * dbl_ps_stride + cb.coef : dbl + cb.coef;
         for (int k = 0; k < cb.n; ++k) s += co[k] * A[(long long)(cb.acc + k) * batch + b];
       }
-    if (gw) gw[p] = s;
-    return;
   }
-  const long long j = idx - n_w;
-  if (j >= (long long)n_x * batch || !gx) return;
+  s = seg_sum_dpp(s, gl);
+  if (valid && g == (1 << gl) - 1) gw[o] = s;
+}
+
+// feature gradients: one thread per (sample, feature)
+__global__ void __launch_bounds__(NTR) k_grad_features(const int *cptr, const Contrib *contribs, const double *A,
+                                                       const double *dbl, const double *dbl_ps, int dbl_ps_stride,
+                                                       int n_w, int n_x, int batch, double *gx) {
+  const long long j = (long long)blockIdx.x * NTR + threadIdx.x;
+  if (j >= (long long)n_x * batch) return;
   const int b = (int)(j / n_x), f = (int)(j % n_x);
   const int p = n_w + f;
   double s = 0.0;

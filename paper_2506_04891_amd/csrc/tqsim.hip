@@ -71,11 +71,19 @@ struct tqs_circuit {
   int *d_cptr = nullptr;
   long long *d_acc_static = nullptr;
   int *d_acc_units = nullptr;
+  int max_units = 1;   // longest per-sample accumulator sum
 };
 
 namespace {
 
 size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+// log2 of the lanes given to a sum of `n` terms: ceil(log2 n), at most a wave
+int ceil_log2(long long n) {
+  int l = 0;
+  while (l < 6 && (1ll << l) < n) ++l;
+  return l;
+}
 
 template <typename V>
 size_t bytes_of(const std::vector<V> &v) {
@@ -84,9 +92,9 @@ size_t bytes_of(const std::vector<V> &v) {
 
 std::once_flag g_attr_once;
 
-template <typename T, int K, bool BWD>
+template <typename T, int K, bool BWD, bool DENSE = false>
 void set_lds_attr() {
-  (void)hipFuncSetAttribute(reinterpret_cast<const void *>(&k_pass<T, K, BWD>),
+  (void)hipFuncSetAttribute(reinterpret_cast<const void *>(&k_pass<T, K, BWD, DENSE>),
                             hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
 }
 
@@ -103,11 +111,17 @@ void set_all_attrs() {
   set_lds_attr<double, 10, true>();
   set_lds_attr<double, 11, true>();
   set_lds_attr<double, 12, true>();
+  set_lds_attr<float, 10, false, true>();
+  set_lds_attr<float, 10, true, true>();
+  set_lds_attr<double, 10, false, true>();
+  set_lds_attr<double, 10, true, true>();
 }
 
 tqs_status upload(tqs_circuit *c) {
   std::lock_guard<std::mutex> lk(c->mu);
   if (c->uploaded) return TQS_OK;
+  c->max_units = 1;
+  for (int u : c->plan.acc_units) c->max_units = std::max(c->max_units, u);
   std::call_once(g_attr_once, set_all_attrs);
   const Plan &P = c->plan;
   struct Part {
@@ -267,9 +281,9 @@ double op_flops_bwd(const DevOp &o) {
   return f;
 }
 
-template <typename T, int K, bool BWD>
+template <typename T, int K, bool BWD, bool DENSE = false>
 void launch_pass_k(const PassArgs<T> &a, int grid, size_t lds, hipStream_t s) {
-  hipLaunchKernelGGL((k_pass<T, K, BWD>), dim3(grid), dim3(1 << (K - RB)), lds, s, a);
+  hipLaunchKernelGGL((k_pass<T, K, BWD, DENSE>), dim3(grid), dim3(1 << (K - RB)), lds, s, a);
 }
 
 template <typename T, bool BWD>
@@ -324,6 +338,15 @@ tqs_status launch_pass(tqs_circuit *c, int pi, int B, const cplx<T> *src0, cplx<
   }
   ProfScope ps(c, s, std::string(BWD ? "pass_bwd_K" : "pass_fwd_K") + std::to_string(d.K) +
                          (sizeof(T) == 8 ? "_c128" : "_c64"), bytes, flops);
+  // passes holding full-layer matrix ops use their own instantiation, so that
+  // the matrix-core code does not raise the register use of the others
+  if (d.dense_off >= 0) {
+    if (d.K != 10) return fail(TQS_EUNSUPPORTED, "dense layers need a 10-bit tile");
+    launch_pass_k<T, 10, BWD, true>(a, grid, lds, s);
+    ps.end();
+    HIP_TRY(hipGetLastError());
+    return TQS_OK;
+  }
   switch (d.K) {
     case 10: launch_pass_k<T, 10, BWD>(a, grid, lds, s); break;
     case 11: launch_pass_k<T, 11, BWD>(a, grid, lds, s); break;
@@ -358,6 +381,7 @@ tqs_status do_prep(tqs_circuit *c, int B, const double *w, const double *x, char
   dim3 grid((B + 63) / 64, (unsigned)P.prep.size());
   ProfScope ps(c, s, "prep", 0.0, 0.0);
   hipLaunchKernelGGL((k_prep<T>), grid, dim3(64), 0, s, a);
+  if (P.dense) hipLaunchKernelGGL((k_prep_dense<T>), dim3(1u << P.nv, (unsigned)P.prep.size()), dim3(64), 0, s, a);
   ps.end();
   HIP_TRY(hipGetLastError());
   return TQS_OK;
@@ -411,9 +435,10 @@ tqs_status expval_t(const tqs_circuit *c, int B, const void *state, double *expz
     hipLaunchKernelGGL((k_expval<T, false>), dim3((unsigned)blocks), dim3(NTE), 0, s, a);
   ps.end();
   HIP_TRY(hipGetLastError());
-  const int tot = B * (P.n + 1);
-  hipLaunchKernelGGL(k_expval_final, dim3(tot), dim3(64), 0, s,
-                     (const double *)(ws + L.ev), expz, norm, P.n, B);
+  const long long tot = (long long)B * (P.n + 1);
+  const int gl = std::min(6, std::max(0, P.n - KE));   // lanes per output: the unit count, up to 64
+  hipLaunchKernelGGL(k_expval_final, dim3((unsigned)(((tot << gl) + NTR - 1) / NTR)), dim3(NTR), 0, s,
+                     (const double *)(ws + L.ev), expz, norm, P.n, B, gl);
   HIP_TRY(hipGetLastError());
   return TQS_OK;
 }
@@ -465,17 +490,26 @@ tqs_status adjoint_t(tqs_circuit *c, int B, const double *w, const double *x, vo
   ProfScope psf(c, s, "grad_finalize", 0.0, 0.0);
   if (P.n_acc > 0) {
     const long long tot = (long long)P.n_acc * B;
-    hipLaunchKernelGGL((k_acc_reduce<T>), dim3((unsigned)tot), dim3(64), 0, s,
+    const int gl = ceil_log2(c->max_units);
+    hipLaunchKernelGGL((k_acc_reduce<T>), dim3((unsigned)(((tot << gl) + NTR - 1) / NTR)), dim3(NTR), 0, s,
                        reinterpret_cast<const T *>(ws + L.partials), (const long long *)c->d_acc_static,
-                       (const int *)c->d_acc_units, P.n_acc, B, A);
+                       (const int *)c->d_acc_units, P.n_acc, B, A, gl);
     HIP_TRY(hipGetLastError());
   }
-  const long long tot = (long long)P.n_weights + (long long)P.n_features * B;
-  if (tot > 0) {
-    hipLaunchKernelGGL(k_grad_combine, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s,
+  if (P.n_weights > 0 && gw) {
+    const int gl = ceil_log2(B);
+    hipLaunchKernelGGL(k_grad_weights, dim3((unsigned)((((long long)P.n_weights << gl) + NTR - 1) / NTR)),
+                       dim3(NTR), 0, s, (const int *)c->d_cptr, (const Contrib *)c->d_contrib, (const double *)A,
+                       (const double *)(ws + L.dbl), (const double *)(ws + L.dbl_ps), P.n_dbl_ps, P.n_weights, B,
+                       gw, gl);
+    HIP_TRY(hipGetLastError());
+  }
+  const long long totx = (long long)P.n_features * B;
+  if (totx > 0 && gx) {
+    hipLaunchKernelGGL(k_grad_features, dim3((unsigned)((totx + NTR - 1) / NTR)), dim3(NTR), 0, s,
                        (const int *)c->d_cptr, (const Contrib *)c->d_contrib, (const double *)A,
-                       (const double *)(ws + L.dbl), (const double *)(ws + L.dbl_ps), P.n_dbl_ps,
-                       P.n_weights, gx ? P.n_features : 0, B, gw, gx);
+                       (const double *)(ws + L.dbl), (const double *)(ws + L.dbl_ps), P.n_dbl_ps, P.n_weights,
+                       P.n_features, B, gx);
     HIP_TRY(hipGetLastError());
   }
   psf.end();
