@@ -43,11 +43,15 @@ def parse():
     # over this many MiB three times: the known-size reference that scales
     # rocprofv3's FETCH_SIZE / WRITE_SIZE readings to bytes
     p.add_argument("--calibrate-copy-mib", type=int, default=0)
+    # instead of the benchmark: time forward + adjoint of small circuits under
+    # each dispatch mode (tile passes per layer, fused tile passes, dense
+    # matrix-core layers) and print one JSON line per case
+    p.add_argument("--dense-sweep", action="store_true")
     return p.parse_args()
 
 
-def traffic_file(kind):
-    return os.path.join(ROOT, "profiles", f"traffic_{kind}_16q_b128.txt")
+def traffic_file(kind, workload="16q_b128"):
+    return os.path.join(ROOT, "profiles", f"traffic_{kind}_{workload}.txt")
 
 
 def roofline(report, traffic_path=None):
@@ -190,6 +194,57 @@ def serving_bench(n_req, n_max, fracs, seed=0, streams=4, budget=160 << 30):
     return out
 
 
+def dense_sweep(iters=30):
+    """Per-call time of forward + <Z> + adjoint for n = 2..6 under each mode;
+    for dense mode also the rate of the dense pass kernels on the matrix cores
+    (8 * 2^n flop per amplitude per dense layer)."""
+    import torch
+    import workloads as W
+    from paper_2506_04891_amd import tqsim as T
+    dev = torch.device("cuda")
+    for n in (2, 4, 5, 6):
+        circuits = [("rot_ring", W.circuit_rot_ring(n, 10, "RY", ("RY", "RZ")), "normal")]
+        if n % 2 == 0:
+            circuits.append(("ionq", W.circuit_ionq(n, 8), "uniform2pi"))
+        for name, layers, dist in circuits:
+            for dt in ("c64", "c128"):
+                for B in (16, 256, 4096):
+                    row = {"n": n, "circuit": name, "dtype": dt, "batch": B}
+                    for mode in ("per_layer", "fused", "dense"):
+                        c = T.Circuit(n, layers, dt, mode=mode)
+                        w, x = W.draw_params(n, layers, B, dist, 0)
+                        wt, xt = torch.tensor(w, device=dev), torch.tensor(x, device=dev)
+                        g = torch.ones((B, n), dtype=torch.float64, device=dev)
+                        st = torch.empty((B, 2 ** n), dtype=c.complex_dtype, device=dev)
+                        ws = c.workspace(B, True, dev)
+
+                        def step():
+                            c.forward(wt, xt, state=st, ws=ws)
+                            c.expval_z(st, ws=ws)
+                            c.adjoint_grad(wt, xt, st, g, ws=ws)
+                        for _ in range(3):
+                            step()
+                        torch.cuda.synchronize()
+                        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                        e0.record()
+                        for _ in range(iters):
+                            step()
+                        e1.record()
+                        torch.cuda.synchronize()
+                        row[mode + "_us"] = round(e0.elapsed_time(e1) / iters * 1e3, 1)
+                        if mode == "dense":
+                            c.profile_report(reset=True)
+                            c.set_profile(True)
+                            step()
+                            c.set_profile(False)
+                            rep = c.profile_report(reset=True)
+                            ms = sum(v["ms"] for k, v in rep.items() if k.startswith("pass"))
+                            fl = sum(v["flops"] for k, v in rep.items() if k.startswith("pass"))
+                            row["dense_pass_us"] = round(ms * 1e3, 1)
+                            row["dense_pass_TFLOPs"] = round(fl / max(ms, 1e-9) / 1e9, 2)
+                    print(json.dumps(row), flush=True)
+
+
 def cpu_baseline(sample=2):
     """The oracle (numpy complex128, per-gate contraction) on `sample` samples
     of each 16-qubit circuit: forward <Z_i> and adjoint gradients."""
@@ -223,6 +278,9 @@ def main():
         sys.exit(1)
     from paper_2506_04891_amd import tqsim as T
     T.lib()   # fails loudly when the HIP library is missing
+    if a.dense_sweep:
+        dense_sweep()
+        return
 
     jobs = [Job("c4a_16q_b128_ionq", a.mode), Job("c4b_16q_b128_ibm", a.mode)]
     ms, wall_ms, rep = time_jobs(jobs, a.steps, a.warmup)
@@ -270,7 +328,7 @@ def main():
         out["q20"] = {"workload": "20 qubits, batch 32, complex64: RX embedding + 6 x [RX, RY, RZ, ZZ ring, "
                                   "CNOT ring], forward <Z_i> + adjoint gradients",
                       "evals_per_s": round(j20.B / (ms20 / 1e3), 1), "ms_per_step": round(ms20, 3),
-                      "roofline": roofline(rep20),
+                      "roofline": roofline(rep20, lambda k: traffic_file(k, "20q_b32")),
                       "kernels": {k: {"count": v["count"], "ms": round(v["ms"], 3)} for k, v in rep20.items()}}
         del j20
     if not a.no_serve:

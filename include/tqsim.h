@@ -151,7 +151,10 @@ tqs_status tqs_adjoint_grad(tqs_circuit *c, int32_t batch, const double *weights
 
 /* Dispatcher override, before the first forward call.  Keys:
  *   "mode"       0 = auto, 1 = per-layer passes (one technique per layer),
- *                2 = fused passes, 3 = dense (full layer unitaries, n <= 8)
+ *                2 = fused passes, 3 = dense: every layer without per-sample
+ *                parameters applied as its full 2^n x 2^n matrix on the matrix
+ *                cores (the unitary operation of Sec. 2.2.1); for n > 6 the
+ *                plan falls back to fused passes
  *   "tile_bits"  0 = auto, else K in [10, 12] for multi-pass plans
  *   "profile"    1 = time every kernel launch with HIP events (any time; not
  *                to be used while the stream is being captured into a graph)

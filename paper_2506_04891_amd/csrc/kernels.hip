@@ -964,26 +964,27 @@ struct Mfma<double> {
 };
 
 // X <- U X (or U^dagger X) for every sample of the tile: out[j][s] =
-// sum_k U[j][k] X[k][s], X[k][s] = tile element s * 2^nv + k.  Complex products
-// as four real MFMA products; 16 x 16 output blocks spread over the waves;
-// results go to the scratch tile S, then back to X.
-template <typename T, int K, bool ADJ>
-__device__ __forceinline__ void dense_apply(const Ctx<T, K> &c, cplx<T> *X, cplx<T> *S, kptr<cplx<T>> U) {
+// sum_k U[j][k] X[k][s], X[k][s] = tile element s * 2^NV + k.  U sits in LDS
+// with row stride 2^NV + 1.  Complex products as four real MFMA products;
+// 16 x 16 output blocks spread over the waves; results go to the scratch tile
+// S, then back to X.
+template <typename T, int K, int NV, bool ADJ>
+__device__ __forceinline__ void dense_apply(const Ctx<T, K> &c, cplx<T> *X, cplx<T> *S, const cplx<T> *U) {
   typedef typename Mfma<T>::V V;
   constexpr int NT = Ctx<T, K>::NT;
-  const int nv = c.nv;
-  const int dim = 1 << nv;
-  const int rb = dim >> 4, cb = (1 << (K - nv)) >> 4;
+  constexpr int DIM = 1 << NV, LDU = DIM + 1;
+  constexpr int RBK = DIM / 16, CBK = (1 << (K - NV)) / 16;
   const int lane = c.tid & 63, wave = c.tid >> 6;
-  for (int blk = wave; blk < rb * cb; blk += NT / 64) {
-    const int mb = blk % rb, nb = blk / rb;
+  for (int blk = wave; blk < RBK * CBK; blk += NT / 64) {
+    const int mb = blk % RBK, nb = blk / RBK;
     V acc_r = {0, 0, 0, 0}, acc_i = {0, 0, 0, 0};
     const int ar = mb * 16 + (lane & 15);
     const int bj = nb * 16 + (lane & 15);
-    for (int kb = 0; kb < (dim >> 2); ++kb) {
+#pragma unroll
+    for (int kb = 0; kb < DIM / 4; ++kb) {
       const int kk = kb * 4 + (lane >> 4);
-      cplx<T> u = ADJ ? cconj(kld(U, (long long)kk * dim + ar)) : kld(U, (long long)ar * dim + kk);
-      const cplx<T> x = X[swz<T>(bj * dim + kk)];
+      const cplx<T> u = ADJ ? cconj(U[kk * LDU + ar]) : U[ar * LDU + kk];
+      const cplx<T> x = X[swz<T>(bj * DIM + kk)];
       acc_r = Mfma<T>::run(u.x, x.x, acc_r);
       acc_r = Mfma<T>::run(-u.y, x.y, acc_r);
       acc_i = Mfma<T>::run(u.x, x.y, acc_i);
@@ -992,7 +993,7 @@ __device__ __forceinline__ void dense_apply(const Ctx<T, K> &c, cplx<T> *X, cplx
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
       const int row = mb * 16 + Mfma<T>::row(lane, r);
-      S[swz<T>(bj * dim + row)] = cmk<T>(acc_r[r], acc_i[r]);
+      S[swz<T>(bj * DIM + row)] = cmk<T>(acc_r[r], acc_i[r]);
     }
   }
   __syncthreads();
@@ -1004,6 +1005,32 @@ __device__ __forceinline__ void dense_apply(const Ctx<T, K> &c, cplx<T> *X, cplx
   __syncthreads();
 }
 
+// One dense stage: stage the layer matrix in LDS, then apply it (forward) or
+// its adjoint to psi and lambda (backward).
+template <typename T, int K, int NV, bool BWD>
+__device__ __forceinline__ void dense_stage(const Ctx<T, K> &c, cplx<T> *Lp, cplx<T> *Ll, cplx<T> *scr,
+                                            kptr<cplx<T>> Ug) {
+  constexpr int NT = Ctx<T, K>::NT;
+  constexpr int DIM = 1 << NV, LDU = DIM + 1;
+  constexpr int PER = DIM * DIM / NT;          // elements per thread
+  constexpr int CH = PER < 8 ? PER : 8;         // loads kept in flight together
+  cplx<T> *U = scr + (1 << K);
+#pragma unroll
+  for (int i0 = 0; i0 < PER; i0 += CH) {
+    cplx<T> t[CH];
+#pragma unroll
+    for (int q = 0; q < CH; ++q) t[q] = kld(Ug, (i0 + q) * NT + c.tid);
+#pragma unroll
+    for (int q = 0; q < CH; ++q) {
+      const int i = (i0 + q) * NT + c.tid;
+      U[(i / DIM) * LDU + (i % DIM)] = t[q];
+    }
+  }
+  __syncthreads();
+  dense_apply<T, K, NV, BWD>(c, Lp, scr, U);
+  if (BWD) dense_apply<T, K, NV, true>(c, Ll, scr, U);
+}
+
 template <typename T, int K, bool BWD, bool DENSE>
 __device__ __forceinline__ void run_stage(const Ctx<T, K> &c, const PassArgs<T> &a, const UStage &S, cplx<T> *Lp,
                           cplx<T> *Ll, const cplx<T> *tab, bool grad_only) {
@@ -1013,8 +1040,11 @@ __device__ __forceinline__ void run_stage(const Ctx<T, K> &c, const PassArgs<T> 
     kptr<cplx<T>> U = a.mats + uni(a.ops[S.op_begin].mat);
     cplx<T> *scr = const_cast<cplx<T> *>(tab) + uni(a.pass->dense_off);
     __syncthreads();
-    dense_apply<T, K, BWD>(c, Lp, scr, U);
-    if (BWD) dense_apply<T, K, true>(c, Ll, scr, U);
+    switch (c.nv) {
+      case 4: dense_stage<T, K, 4, BWD>(c, Lp, Ll, scr, U); break;
+      case 5: dense_stage<T, K, 5, BWD>(c, Lp, Ll, scr, U); break;
+      default: dense_stage<T, K, 6, BWD>(c, Lp, Ll, scr, U); break;
+    }
     return;
   }
   if (op0_kind == OP_PERM) {

@@ -1069,8 +1069,9 @@ static std::string emit(Plan &P) {
         o.kind = OP_DENSE;
         o.mat = op_mat[oi_ir];
         if (d.dense_off < 0) {
+          // scratch tile, then the layer matrix staged with a padded row stride
           d.dense_off = d.diag_lds;
-          d.diag_lds += 1 << K;
+          d.diag_lds += (1 << K) + (1 << P.nv) * ((1 << P.nv) + 1);
         }
       } else if (op.kind == IR_GRAD1) {
         o.kind = OP_GRAD1;

@@ -3,6 +3,9 @@
     python -m paper_2506_04891_amd.rocprof_summary trace RUN_results.db --command "..."
         per-kernel calls, total and average duration (kernel trace + stats run)
 
+    python -m paper_2506_04891_amd.rocprof_summary counters RUN_results.db --command "..."
+        per-kernel averages of every counter collected (one --pmc run)
+
     python -m paper_2506_04891_amd.rocprof_summary traffic --fetch F.db --write W.db \
         --kernel SUBSTR --copy-kernel SUBSTR --copy-bytes N --command-fetch "..." --command-write "..."
         HBM bytes per launch of one kernel from FETCH_SIZE / WRITE_SIZE counter
@@ -80,6 +83,29 @@ def _counter(db, counter):
     return out
 
 
+def counters_summary(db, command):
+    con = sqlite3.connect(db)
+    rows = con.execute("select dispatch_id, kernel_name, counter_name, value from counters_collection").fetchall()
+    con.close()
+    per = collections.defaultdict(lambda: collections.defaultdict(float))
+    names = {}
+    for d, k, c, v in rows:
+        per[d][c] += v
+        names[d] = k
+    agg = collections.OrderedDict()
+    for d, cs in per.items():
+        a = agg.setdefault(names[d], collections.defaultdict(list))
+        for c, v in cs.items():
+            a[c].append(v)
+    out = [f"command: {command}", f"database: {os.path.basename(db)}",
+           "per-dispatch averages, summed over counter instances"]
+    for k, cs in agg.items():
+        n = len(next(iter(cs.values())))
+        vals = " ".join(f"{c}={sum(v) / len(v):.4g}" for c, v in sorted(cs.items()))
+        out.append(f"{k} | dispatches={n} | {vals}")
+    return "\n".join(out)
+
+
 def _pick(per_kernel, sub):
     keys = [k for k in per_kernel if sub in k]
     if len(keys) != 1:
@@ -145,6 +171,9 @@ def main(argv=None):
     t = sub.add_parser("trace")
     t.add_argument("db")
     t.add_argument("--command", required=True)
+    q = sub.add_parser("counters")
+    q.add_argument("db")
+    q.add_argument("--command", required=True)
     r = sub.add_parser("traffic")
     r.add_argument("--fetch", required=True)
     r.add_argument("--write", required=True)
@@ -156,7 +185,12 @@ def main(argv=None):
     r.add_argument("--command-write", required=True)
     r.add_argument("--sha", default=None)
     a = p.parse_args(argv)
-    print(trace_summary(a.db, a.command) if a.cmd == "trace" else traffic_summary(a))
+    if a.cmd == "trace":
+        print(trace_summary(a.db, a.command))
+    elif a.cmd == "counters":
+        print(counters_summary(a.db, a.command))
+    else:
+        print(traffic_summary(a))
 
 
 if __name__ == "__main__":
