@@ -140,10 +140,11 @@ def time_jobs(jobs, steps, warmup):
     return ms, wall / steps * 1e3, merged
 
 
-def serving_bench(n_req, n_max, fracs, seed=0, streams=4, budget=160 << 30):
+def serving_bench(n_req, n_max, fracs, seed=0, streams=4, budget=160 << 30, heavy=256 << 20):
     """Continuous batching vs the plain per-request path on one Poisson trace of
     rotation + CNOT-ring circuits (qubits U{6..n_max}, batch log-U[1, 512],
-    blocks U{2..20}, 30% forward+gradient)."""
+    blocks U{2..20}, 30% forward+gradient).  Launches reserving more than
+    `heavy` bytes fill the device alone and run one at a time."""
     import numpy as np
     import workloads as W
     from paper_2506_04891_amd.serve import GpuExecutor, Request, Server
@@ -157,7 +158,7 @@ def serving_bench(n_req, n_max, fracs, seed=0, streams=4, budget=160 << 30):
         return reqs
 
     def run(reqs, plain, ex):
-        srv = Server(ex, budget_bytes=budget, streams=streams, plain=plain)
+        srv = Server(ex, budget_bytes=budget, streams=streams, plain=plain, heavy_bytes=heavy)
         t0 = time.perf_counter()
         futs = []
         for ta, r in reqs:
@@ -180,7 +181,8 @@ def serving_bench(n_req, n_max, fracs, seed=0, streams=4, budget=160 << 30):
     sat = run([(0.0, r) for _, r in make(1e6)], False, ex)
     req_per_s = sat["requests"] / max(1e-9, (sat["evals"] / max(sat["evals_per_s"], 1e-9)))
     out = {"trace": f"{n_req} requests, qubits U{{6..{n_max}}}, batch log-U[1,512], blocks U{{2..20}}, "
-                    f"30% forward+gradient, seed {seed}; {streams} streams; warm circuits and graphs",
+                    f"30% forward+gradient, seed {seed}; {streams} streams, one launch above "
+                    f"{heavy >> 20} MiB at a time; warm circuits and graphs",
            "saturation": {"requests_per_s": round(req_per_s, 1), "evals_per_s": round(sat["evals_per_s"], 1)},
            "points": []}
     for frac in fracs:

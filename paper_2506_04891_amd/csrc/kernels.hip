@@ -644,6 +644,7 @@ struct PassArgs {
   kptr<DevDiag> diags;
   kptr<DevTerm> terms;
   kptr<DevPerm> perms;
+  kptr<DevGroup> groups;
   kptr<cplx<T>> mats;
   kptr<cplx<T>> mats_ps;
   int mats_ps_stride;
@@ -766,6 +767,27 @@ __device__ __forceinline__ void u1_dispatch(cplx<T> (&v)[NREG], const cplx<T> m[
       case 2: TQS_CASE_MARK(c2); u1_apply<T, 2, ADJ>(v, m); TQS_CASE_MARK(ec2); break;
       default: TQS_CASE_MARK(c3); u1_apply<T, 3, ADJ>(v, m); TQS_CASE_MARK(ec3); break;
     }
+  }
+}
+
+// A group of complex 2x2 gates on the register bits of MASK, each with its
+// own matrix m[r]; straight-line code per mask.
+template <typename T, int MASK, bool ADJ>
+__device__ __forceinline__ void u1g_apply(cplx<T> (&v)[NREG], const cplx<T> (&m)[RB][4]) {
+  if (MASK & 1) u1_apply<T, 0, ADJ>(v, m[0]);
+  if (MASK & 2) u1_apply<T, 1, ADJ>(v, m[1]);
+  if (MASK & 4) u1_apply<T, 2, ADJ>(v, m[2]);
+  if (MASK & 8) u1_apply<T, 3, ADJ>(v, m[3]);
+}
+
+template <typename T, bool ADJ>
+__device__ __forceinline__ void u1g_dispatch(cplx<T> (&v)[NREG], const cplx<T> (&m)[RB][4], int mask) {
+  switch (mask) {
+#define X(k) \
+  case k: { TQS_CASE_MARK(g##k); u1g_apply<T, k, ADJ>(v, m); TQS_CASE_MARK(eg##k); break; }
+    X(3) X(5) X(6) X(7) X(9) X(10) X(11) X(12) X(13) X(14) X(15)
+#undef X
+    default: break;
   }
 }
 
@@ -1126,10 +1148,44 @@ __device__ __forceinline__ void run_stage(const Ctx<T, K> &c, const PassArgs<T> 
       }
       if (op.kind == OP_U1) {
         cplx<T> m[4];
-        m[0] = kld(mg, 0); m[1] = kld(mg, 1); m[2] = kld(mg, 2); m[3] = kld(mg, 3);
+        if (op.flags & F_PERSAMPLE) {
+          m[0] = kld(mg, 0); m[1] = kld(mg, 1); m[2] = kld(mg, 2); m[3] = kld(mg, 3);
+        } else {
+          // shared matrix: a uniform address, so scalar loads
+          kptr<cplx<T>> ms = a.mats + op.mat;
+          m[0] = kld(ms, 0); m[1] = kld(ms, 1); m[2] = kld(ms, 2); m[3] = kld(ms, 3);
+        }
         u1_dispatch<T, BWD>(vp, m, op.r0, op.flags);
         if (BWD) u1_dispatch<T, true>(vl, m, op.r0, op.flags);
       }
+    } else if (op.kind == OP_U1G) {
+      kptr<DevGroup> gp = a.groups + op.aux;
+      cplx<T> m[RB][4];
+#pragma unroll
+      for (int r = 0; r < RB; ++r) {
+        const int mo = uni(gp->mat[r]);
+        kptr<cplx<T>> ms = a.mats + (mo < 0 ? 0 : mo);
+#pragma unroll
+        for (int q = 0; q < 4; ++q) m[r][q] = kld(ms, q);
+      }
+      if (BWD && (op.flags & F_GRAD)) {
+        // the members commute, so every gradient is taken at the group's output
+#pragma unroll
+        for (int r = 0; r < RB; ++r) {
+          const int ga = uni(gp->acc[r]);
+          if (ga < 0) continue;
+          T sx = 0, sy = 0, sz = 0;
+          if (r == 0) u1_grad<T, 0>(vp, vl, sx, sy, sz);
+          if (r == 1) u1_grad<T, 1>(vp, vl, sx, sy, sz);
+          if (r == 2) u1_grad<T, 2>(vp, vl, sx, sy, sz);
+          if (r == 3) u1_grad<T, 3>(vp, vl, sx, sy, sz);
+          write_acc(c, a, sx, ga + 0);
+          write_acc(c, a, sy, ga + 1);
+          write_acc(c, a, sz, ga + 2);
+        }
+      }
+      u1g_dispatch<T, BWD>(vp, m, op.r0);
+      if (BWD) u1g_dispatch<T, true>(vl, m, op.r0);
     } else if (op.kind == OP_U2) {
       kptr<cplx<T>> mg = op_mat(a, op, s_thr);
       if (BWD && (op.flags & F_GRAD)) {

@@ -34,6 +34,8 @@ enum OpKind : int32_t {
   OP_PERM = 5,   // in-tile GF(2)-affine permutation (resident passes only)
   OP_DENSE = 6,  // full 2^nv x 2^nv layer unitary on every sample of the tile (MFMA)
   OP_GRAD2 = 7,  // gradient-only Pauli-pair sum on register bits (r0, r1) (no gate)
+  OP_U1G = 8,    // complex 2x2 gates on several register bits at once: r0 = bit mask,
+                 // aux = DevGroup index (the gates act on distinct bits, so they commute)
 };
 
 enum OpFlag : int32_t {
@@ -88,6 +90,14 @@ struct DevTerm {
   int32_t per_sample;
   int32_t acc;            // accumulators: P_a, P_b, P_ab (2-bit) or P_a (1-bit); -1 none
   int32_t tab;            // 0: TL, 1: TH, 2: constant
+};
+
+// Members of an OP_U1G group, by register bit: matrix offset and first gradient
+// accumulator (3 per gate: the X, Y, Z Pauli sums), -1 when the bit has no gate
+// or the gate no parameter.
+struct DevGroup {
+  int32_t mat[RB];
+  int32_t acc[RB];
 };
 
 // In-tile permutation: dst tile index t takes src = xor of cols[i] over set bits i of t, ^ cxor.

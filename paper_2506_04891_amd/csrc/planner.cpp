@@ -621,6 +621,51 @@ struct Sched {
 
 }  // namespace
 
+// Runs of consecutive complex single-qubit ops (shared matrices) on distinct
+// register bits of one stage become one OP_U1G op: they commute, so the kernel
+// applies them back to back and takes their gradients at the group's output.
+static void group_u1(Plan &P, int begin) {
+  auto eligible = [](const DevOp &o) {
+    return o.kind == OP_U1 && !(o.flags & (F_PERSAMPLE | F_REAL | F_DIAGONAL));
+  };
+  std::vector<DevOp> out;
+  size_t i = begin;
+  while (i < P.dop.size()) {
+    if (!eligible(P.dop[i])) {
+      out.push_back(P.dop[i++]);
+      continue;
+    }
+    size_t j = i;
+    int mask = 0;
+    while (j < P.dop.size() && eligible(P.dop[j]) && !(mask & (1 << P.dop[j].r0))) mask |= 1 << P.dop[j++].r0;
+    if (j - i < 2) {
+      out.push_back(P.dop[i++]);
+      continue;
+    }
+    DevGroup g;
+    DevOp o;
+    std::memset(&o, 0, sizeof o);
+    for (int r = 0; r < RB; ++r) g.mat[r] = g.acc[r] = -1;
+    for (size_t k = i; k < j; ++k) {
+      const DevOp &u = P.dop[k];
+      g.mat[u.r0] = u.mat;
+      if (u.flags & F_GRAD) {
+        g.acc[u.r0] = u.acc;
+        o.flags |= F_GRAD;
+      }
+    }
+    o.kind = OP_U1G;
+    o.r0 = mask;
+    o.acc = -1;
+    o.aux = (int)P.dgroup.size();
+    P.dgroup.push_back(g);
+    out.push_back(o);
+    i = j;
+  }
+  P.dop.resize(begin);
+  P.dop.insert(P.dop.end(), out.begin(), out.end());
+}
+
 static std::string schedule(Plan &P, int K) {
   const int n = P.n;
   P.passes.clear();
@@ -781,6 +826,7 @@ static std::string emit(Plan &P) {
   P.ddiag.clear();
   P.dterm.clear();
   P.dperm.clear();
+  P.dgroup.clear();
   P.prep.clear();
   P.contribs.clear();
   P.n_mats = P.n_mats_ps = P.n_dbl = P.n_dbl_ps = 0;
@@ -1159,6 +1205,7 @@ static std::string emit(Plan &P) {
       for (int k = 0; k < RB; ++k) st.rbits[k] = S[k];
       for (int j : stage_ops) emit_op(P.ops[po[j]], po[j], S);
       if (!emit_error.empty()) return emit_error;
+      group_u1(P, st.op_begin);
       st.op_end = (int)P.dop.size();
       P.dstage.push_back(st);
       prev_regs = S;
@@ -1303,11 +1350,15 @@ std::string describe_plan(const Plan &P) {
   for (size_t p = 0; p < P.passes.size(); ++p) {
     const PlanPass &pp = P.passes[p];
     const DevPass &d = P.dpass[p];
-    int nu1 = 0, nu2 = 0, ndg = 0, npm = 0, ndense = 0;
+    int nu1 = 0, nu2 = 0, ndg = 0, npm = 0, ndense = 0, ngrp = 0;
     for (int s = d.stage_begin; s < d.stage_begin + d.n_stages; ++s)
       for (int oi = P.dstage[s].op_begin; oi < P.dstage[s].op_end; ++oi) {
         const int k = P.dop[oi].kind;
         nu1 += k == OP_U1;
+        if (k == OP_U1G) {
+          nu1 += __builtin_popcount((unsigned)P.dop[oi].r0);
+          ++ngrp;
+        }
         nu2 += k == OP_U2;
         ndg += k == OP_DIAG;
         npm += k == OP_PERM;
@@ -1318,7 +1369,8 @@ std::string describe_plan(const Plan &P) {
     o << "],\"load\":\"" << (pp.load_mode == LOAD_EMBED ? "embed" : (pp.has_load ? "gather" : "tile"))
       << "\",\"store\":\"" << (pp.has_store ? "scatter" : "tile") << "\",\"bwd_only\":"
       << (pp.bwd_only ? "true" : "false") << ",\"stages\":" << d.n_stages << ",\"u1\":" << nu1
-      << ",\"u2\":" << nu2 << ",\"diag\":" << ndg << ",\"perm\":" << npm << ",\"dense\":" << ndense
+      << ",\"u1_groups\":" << ngrp << ",\"u2\":" << nu2 << ",\"diag\":" << ndg << ",\"perm\":" << npm
+      << ",\"dense\":" << ndense
       << ",\"grad_wires\":"
       << pp.grad_wires.size() << ",\"n_acc\":" << d.n_acc << "}";
   }

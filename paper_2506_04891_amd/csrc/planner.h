@@ -71,6 +71,7 @@ struct Plan {
   std::vector<DevDiag> ddiag;
   std::vector<DevTerm> dterm;
   std::vector<DevPerm> dperm;
+  std::vector<DevGroup> dgroup;
   std::vector<PrepItem> prep;
   std::vector<Contrib> contribs;
   std::vector<int> cptr;                 // CSR over params: weights then features

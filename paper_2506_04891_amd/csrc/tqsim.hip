@@ -65,6 +65,7 @@ struct tqs_circuit {
   DevDiag *d_diag = nullptr;
   DevTerm *d_term = nullptr;
   DevPerm *d_perm = nullptr;
+  DevGroup *d_group = nullptr;
   PrepItem *d_prep = nullptr;
   Factor *d_fac = nullptr;
   Contrib *d_contrib = nullptr;
@@ -136,6 +137,7 @@ tqs_status upload(tqs_circuit *c) {
       {P.ddiag.data(), bytes_of(P.ddiag), (void **)&c->d_diag},
       {P.dterm.data(), bytes_of(P.dterm), (void **)&c->d_term},
       {P.dperm.data(), bytes_of(P.dperm), (void **)&c->d_perm},
+      {P.dgroup.data(), bytes_of(P.dgroup), (void **)&c->d_group},
       {P.prep.data(), bytes_of(P.prep), (void **)&c->d_prep},
       {P.factors.data(), bytes_of(P.factors), (void **)&c->d_fac},
       {P.contribs.data(), bytes_of(P.contribs), (void **)&c->d_contrib},
@@ -299,6 +301,7 @@ tqs_status launch_pass(tqs_circuit *c, int pi, int B, const cplx<T> *src0, cplx<
   a.diags = kc(c->d_diag);
   a.terms = kc(c->d_term);
   a.perms = kc(c->d_perm);
+  a.groups = kc(c->d_group);
   a.mats = kc(reinterpret_cast<const cplx<T> *>(ws + L.mats));
   a.mats_ps = kc(reinterpret_cast<const cplx<T> *>(ws + L.mats_ps));
   a.mats_ps_stride = P.n_mats_ps;
@@ -326,9 +329,15 @@ tqs_status launch_pass(tqs_circuit *c, int pi, int B, const cplx<T> *src0, cplx<
     double f = 0;
     for (int st = d.stage_begin; st < d.stage_begin + d.n_stages; ++st)
       for (int oi = P.dstage[st].op_begin; oi < P.dstage[st].op_end; ++oi) {
-        if (P.dop[oi].kind == OP_DENSE)
+        if (P.dop[oi].kind == OP_DENSE) {
           f += (BWD ? 2.0 : 1.0) * dense_flops(P.nv);
-        else
+        } else if (P.dop[oi].kind == OP_U1G) {
+          // each member: a complex 2x2 (14 flop/amp), backward twice that plus
+          // its Pauli sums when it has parameters
+          const DevGroup &g = P.dgroup[P.dop[oi].aux];
+          for (int r = 0; r < RB; ++r)
+            if (g.mat[r] >= 0) f += BWD ? 28.0 + (g.acc[r] >= 0 ? 18.0 : 0.0) : 14.0;
+        } else
           f += BWD ? op_flops_bwd(P.dop[oi]) : op_flops(P.dop[oi]);
       }
     if (BWD)

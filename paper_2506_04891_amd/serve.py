@@ -14,6 +14,10 @@ forward + gradient) arrive at any time.  A scheduler thread
   on the device, replaying a captured HIP graph for small circuits (launch
   latency dominates there), and frees the reservation when the launch's event
   completes, admitting waiting requests as memory and streams free up;
+* keeps at most one *heavy* launch (reservation above ``heavy_bytes``) in
+  flight: a large circuit saturates the device by itself, so two of them
+  sharing it only stretch both, while small requests still overlap with it
+  and are admitted past a heavy request that has to wait;
 * records arrival -> result latency per request.
 
 ``Server(..., plain=True)`` is the plain per-request path used as the
@@ -27,6 +31,7 @@ host-only executor to check the scheduling logic.
 from __future__ import annotations
 
 import collections
+import gc
 import math
 import threading
 import time
@@ -93,6 +98,7 @@ class Group:
         self.reserve = 0
         self.handle = None
         self.slot = None
+        self.heavy = False
 
 
 class Server:
@@ -100,11 +106,16 @@ class Server:
 
     budget_bytes: device memory that admitted launches may reserve together.
     streams: launches in flight at once.  max_rows: rows per coalesced launch.
+    heavy_bytes: launches reserving more are heavy; one heavy launch at a time
+    (None: no limit).
     plain: the per-request baseline (one stream, FIFO, no coalescing)."""
 
     def __init__(self, executor, budget_bytes, streams=4, max_rows=1024, plain=False, poll_s=50e-6,
-                 paused=False):
+                 paused=False, heavy_bytes=None):
         self.ex = executor
+        self.heavy_bytes = None if heavy_bytes is None else int(heavy_bytes)
+        self._heavy_inflight = 0
+        self.max_heavy_inflight = 0
         self._paused = paused
         self.budget = int(budget_bytes)
         self.streams = 1 if plain else int(streams)
@@ -180,13 +191,22 @@ class Server:
                 "errors": len(self.errors)}
 
     # ---------------------------------------------------------- scheduler --
+    def _is_heavy(self, req):
+        return (self.heavy_bytes is not None and not self.plain
+                and self.ex.reserve(Group(req.key, [req])) > self.heavy_bytes)
+
     def _next_group(self):
-        """Oldest pending key; its requests up to max_rows (one request when plain)."""
-        while self._order:
-            key = self._order[0]
+        """Oldest pending key (skipping heavy ones while a heavy launch is in
+        flight); its requests up to max_rows (one request when plain)."""
+        i = 0
+        while i < len(self._order):
+            key = self._order[i]
             q = self._pending.get(key)
             if not q:
-                self._order.popleft()
+                del self._order[i]
+                continue
+            if self._heavy_inflight and self._is_heavy(q[0]):
+                i += 1
                 continue
             reqs = [q.popleft()]
             if not self.plain:
@@ -194,8 +214,8 @@ class Server:
                 while q and rows + q[0].batch <= self.max_rows:
                     rows += q[0].batch
                     reqs.append(q.popleft())
-            # keep arrival order: drop this key's entries that were consumed
-            self._order.popleft()
+            # keep arrival order: drop this key's entry that was consumed
+            del self._order[i]
             return Group(key, reqs)
         return None
 
@@ -231,8 +251,10 @@ class Server:
                         break
                     g.reserve = self.ex.reserve(g)
                     avail = self.budget - self._reserved
-                    # shrink a coalesced group until it fits the free budget
-                    while g.reserve > avail and len(g.reqs) > 1:
+                    # shrink a coalesced group until it fits the free budget (and,
+                    # while a heavy launch runs, until it is not heavy itself)
+                    while (g.reserve > avail or (self._heavy_inflight and self.heavy_bytes is not None
+                                                 and g.reserve > self.heavy_bytes)) and len(g.reqs) > 1:
                         last = g.reqs.pop()
                         g.rows -= last.batch
                         self._pending[g.key].appendleft(last)
@@ -242,6 +264,9 @@ class Server:
                         self._requeue_front(g)     # wait for memory to free up
                         break
                     g.slot = self._free_slots.pop()
+                    g.heavy = self.heavy_bytes is not None and not self.plain and g.reserve > self.heavy_bytes
+                    self._heavy_inflight += g.heavy
+                    self.max_heavy_inflight = max(self.max_heavy_inflight, self._heavy_inflight)
                     self._reserved += g.reserve
                     self.peak_reserved = max(self.peak_reserved, self._reserved)
                     try:
@@ -264,6 +289,7 @@ class Server:
 
     def _release(self, g):
         self._reserved -= g.reserve
+        self._heavy_inflight -= g.heavy
         self._free_slots.append(g.slot)
 
     def _finish(self, g):
@@ -470,8 +496,19 @@ class GpuExecutor:
         e, gx = self._run(c, static["x"], static["g"], key[2], static["w"])
         torch.cuda.current_stream().synchronize()
         graph = torch.cuda.CUDAGraph()
-        with torch.cuda.graph(graph, stream=stream):
-            e, gx = self._run(c, static["x"], static["g"], key[2], static["w"])
+        # nothing may free device memory while the capture runs: destroy dropped
+        # circuits now and keep the garbage collector off until the capture ends
+        from .tqsim import release_pending
+        gc.collect()
+        release_pending()
+        gc_was_on = gc.isenabled()
+        gc.disable()
+        try:
+            with torch.cuda.graph(graph, stream=stream):
+                e, gx = self._run(c, static["x"], static["g"], key[2], static["w"])
+        finally:
+            if gc_was_on:
+                gc.enable()
         static["e"], static["gx"] = e, gx
         ent = {"graph": graph, "static": static, "busy": True}
         with self._lock:

@@ -8,7 +8,9 @@ import fails loudly -- there is no other execution path.
 """
 from __future__ import annotations
 
+import atexit
 import ctypes
+import threading
 import json
 import os
 
@@ -102,6 +104,28 @@ def _stream(stream):
     return ctypes.c_void_p(s.cuda_stream)
 
 
+# Circuits dropped by Python are destroyed later, at a safe point: destroying one
+# frees device memory, which would invalidate a HIP graph capture that happens
+# to be running when the garbage collector finalises the circuit.
+_released = []
+_released_lock = threading.Lock()
+
+
+def release_pending():
+    """Destroy the circuits dropped since the last call.  Called when a circuit
+    is created and before the serving executor captures a graph; call it at any
+    other point where no graph capture is in progress."""
+    with _released_lock:
+        hs = list(_released)
+        _released.clear()
+    for h in hs:
+        if _lib is not None:
+            _lib.tqs_circuit_destroy(h)
+
+
+atexit.register(release_pending)
+
+
 class Circuit:
     """A compiled circuit: ``Circuit(n, layers, dtype="c64")``.
 
@@ -111,6 +135,7 @@ class Circuit:
 
     def __init__(self, n, layers, dtype="c64", mode="auto", tile_bits=0):
         L = lib()
+        release_pending()
         self.n = int(n)
         self.dtype = dtype
         self.layers = list(layers)
@@ -129,8 +154,9 @@ class Circuit:
 
     def __del__(self):
         h = getattr(self, "_h", None)
-        if h is not None and _lib is not None:
-            _lib.tqs_circuit_destroy(h)
+        if h is not None:
+            with _released_lock:
+                _released.append(h)
             self._h = None
 
     @property

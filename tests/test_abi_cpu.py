@@ -137,3 +137,19 @@ def test_dense_mode_plans(n):
     else:
         assert p["mode"] != "dense"
         assert all(q["dense"] == 0 for q in p["passes"])
+
+
+def test_dropped_circuits_are_destroyed_at_safe_points():
+    """Dropping a circuit only queues its destruction (freeing device memory
+    inside a running graph capture would invalidate it); release_pending() and
+    the next circuit creation destroy the queued ones."""
+    T = _lib()
+    from paper_2506_04891_amd import tqsim
+    tqsim.release_pending()
+    c = T.Circuit(4, W.circuit_rot_ring(4, 1), "c64")
+    del c
+    assert len(tqsim._released) == 1
+    keep = T.Circuit(3, W.circuit_rot_ring(3, 1), "c64")
+    assert len(tqsim._released) == 0
+    del keep
+    tqsim.release_pending()

@@ -112,3 +112,21 @@ def test_plain_path_is_one_request_per_launch():
 
 def test_bucket():
     assert [bucket(b) for b in (1, 2, 3, 5, 8, 9, 512, 513)] == [1, 2, 4, 8, 8, 16, 512, 1024]
+
+
+def test_one_heavy_launch_at_a_time():
+    """Launches reserving more than heavy_bytes never overlap each other, small
+    ones still overlap with them, and every result equals the request alone."""
+    reqs = _requests(40, seed=6, b_max=32)
+    row = 1 << 20
+    ex = HostExecutor(oracle_fn, delay=0.004, row_bytes=row)
+    srv = Server(ex, budget_bytes=1 << 40, streams=4, heavy_bytes=8 * row, paused=True)
+    futs = [srv.submit(r) for r in reqs]
+    srv.resume()
+    res = [f.result(timeout=60) for f in futs]
+    srv.close()
+    assert srv.max_heavy_inflight == 1
+    assert ex.max_concurrent > 1
+    assert any(bucket(r.batch) > 8 for r in reqs) and any(bucket(r.batch) <= 8 for r in reqs)
+    for r, got in zip(reqs, res):
+        np.testing.assert_array_equal(got.expz, oracle_fn(r).expz)
