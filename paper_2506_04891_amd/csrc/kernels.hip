@@ -838,6 +838,57 @@ __device__ __forceinline__ void u2_apply_any(cplx<T> (&v)[NREG], kptr<cplx<T>> m
   }
 }
 
+// Two structured gates of one kind on disjoint register-bit pairs (a,b), (c,d),
+// the pair holding bit 0 first; key = a<<6 | b<<4 | c<<2 | d.
+#define TQS_U2G_CASES(X)                                                                      \
+  X(0, 1, 2, 3) X(0, 1, 3, 2) X(1, 0, 2, 3) X(1, 0, 3, 2) X(0, 2, 1, 3) X(0, 2, 3, 1) X(2, 0, 1, 3) \
+  X(2, 0, 3, 1) X(0, 3, 1, 2) X(0, 3, 2, 1) X(3, 0, 1, 2) X(3, 0, 2, 1)
+
+template <typename T, bool ADJ, int KIND>
+__device__ __forceinline__ void u2g_dispatch_k(cplx<T> (&v)[NREG], kptr<cplx<T>> m0, kptr<cplx<T>> m1, int key) {
+  switch (key) {
+#define X(a, b, c, d)                                                                    \
+  case (a << 6 | b << 4 | c << 2 | d): {                                                 \
+    TQS_CASE_MARK(h##a##b##c##d##_##KIND);                                               \
+    u2s_apply<T, a, b, ADJ, KIND>(v, m0);                                                \
+    u2s_apply<T, c, d, ADJ, KIND>(v, m1);                                                \
+    TQS_CASE_MARK(eh##a##b##c##d##_##KIND);                                              \
+    break;                                                                               \
+  }
+    TQS_U2G_CASES(X)
+#undef X
+    default: break;
+  }
+}
+
+template <typename T, bool ADJ>
+__device__ __forceinline__ void u2g_dispatch(cplx<T> (&v)[NREG], kptr<cplx<T>> m0, kptr<cplx<T>> m1, int key,
+                                             int sub) {
+  if (sub == U2_MS)
+    u2g_dispatch_k<T, ADJ, U2_MS>(v, m0, m1, key);
+  else
+    u2g_dispatch_k<T, ADJ, U2_ECR>(v, m0, m1, key);
+}
+
+// X(x)X sums of both pairs of a group, taken at the group's output.
+template <typename T>
+__device__ __forceinline__ void u2g_grad_xx(const cplx<T> (&p)[NREG], const cplx<T> (&l)[NREG], int key, T &g0,
+                                            T &g1) {
+  switch (key) {
+#define X(a, b, c, d)                                             \
+  case (a << 6 | b << 4 | c << 2 | d): {                          \
+    TQS_CASE_MARK(x##a##b##c##d);                                 \
+    g0 = u2s_grad<T, a, b, true>(p, l);                           \
+    g1 = u2s_grad<T, c, d, true>(p, l);                           \
+    TQS_CASE_MARK(ex##a##b##c##d);                                \
+    break;                                                        \
+  }
+    TQS_U2G_CASES(X)
+#undef X
+    default: g0 = g1 = T(0); break;
+  }
+}
+
 template <typename T, bool XX>
 __device__ __forceinline__ T u2s_grad_dispatch(const cplx<T> (&p)[NREG], const cplx<T> (&l)[NREG], int r0,
                                                int r1) {
@@ -1186,6 +1237,18 @@ __device__ __forceinline__ void run_stage(const Ctx<T, K> &c, const PassArgs<T> 
       }
       u1g_dispatch<T, BWD>(vp, m, op.r0);
       if (BWD) u1g_dispatch<T, true>(vl, m, op.r0);
+    } else if (op.kind == OP_U2G) {
+      kptr<DevGroup> gp = a.groups + op.aux;
+      kptr<cplx<T>> m0 = a.mats + uni(gp->mat[0]), m1 = a.mats + uni(gp->mat[1]);
+      if (BWD && (op.flags & F_GRAD)) {
+        T g0, g1;
+        u2g_grad_xx(vp, vl, op.r0, g0, g1);
+        const int a0 = uni(gp->acc[0]), a1 = uni(gp->acc[1]);
+        if (a0 >= 0) write_acc(c, a, g0, a0);
+        if (a1 >= 0) write_acc(c, a, g1, a1);
+      }
+      u2g_dispatch<T, BWD>(vp, m0, m1, op.r0, op.sub);
+      if (BWD) u2g_dispatch<T, true>(vl, m0, m1, op.r0, op.sub);
     } else if (op.kind == OP_U2) {
       kptr<cplx<T>> mg = op_mat(a, op, s_thr);
       if (BWD && (op.flags & F_GRAD)) {

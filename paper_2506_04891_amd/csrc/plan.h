@@ -36,6 +36,8 @@ enum OpKind : int32_t {
   OP_GRAD2 = 7,  // gradient-only Pauli-pair sum on register bits (r0, r1) (no gate)
   OP_U1G = 8,    // complex 2x2 gates on several register bits at once: r0 = bit mask,
                  // aux = DevGroup index (the gates act on distinct bits, so they commute)
+  OP_U2G = 9,    // two structured 4x4 gates of one kind (sub) on disjoint register-bit
+                 // pairs: r0 = a<<6 | b<<4 | c<<2 | d for pairs (a,b), (c,d); aux = DevGroup
 };
 
 enum OpFlag : int32_t {
@@ -94,7 +96,8 @@ struct DevTerm {
 
 // Members of an OP_U1G group, by register bit: matrix offset and first gradient
 // accumulator (3 per gate: the X, Y, Z Pauli sums), -1 when the bit has no gate
-// or the gate no parameter.
+// or the gate no parameter.  OP_U2G uses slots 0 and 1 for its two pairs (one
+// accumulator per gate).
 struct DevGroup {
   int32_t mat[RB];
   int32_t acc[RB];

@@ -666,6 +666,53 @@ static void group_u1(Plan &P, int begin) {
   P.dop.insert(P.dop.end(), out.begin(), out.end());
 }
 
+// Pairs of consecutive structured MS or ECR ops of one stage on disjoint
+// register-bit pairs become one OP_U2G op (they commute).
+static void group_u2(Plan &P, int begin) {
+  auto eligible = [](const DevOp &o) {
+    return o.kind == OP_U2 && !(o.flags & F_PERSAMPLE) && (o.sub == U2_MS || o.sub == U2_ECR);
+  };
+  std::vector<DevOp> out;
+  size_t i = begin;
+  while (i < P.dop.size()) {
+    const DevOp &x = P.dop[i];
+    if (i + 1 < P.dop.size() && eligible(x) && eligible(P.dop[i + 1]) && P.dop[i + 1].sub == x.sub) {
+      DevOp y = P.dop[i + 1];
+      DevOp f = x;
+      const int mx = (1 << x.r0) | (1 << x.r1), my = (1 << y.r0) | (1 << y.r1);
+      if (!(mx & my)) {
+        // the pair holding register bit 0 goes first
+        if (!(my & 1) && !(mx & 1)) {
+          out.push_back(P.dop[i++]);
+          continue;
+        }
+        if (my & 1) std::swap(f, y);
+        DevGroup g;
+        for (int r = 0; r < RB; ++r) g.mat[r] = g.acc[r] = -1;
+        g.mat[0] = f.mat;
+        g.mat[1] = y.mat;
+        DevOp o;
+        std::memset(&o, 0, sizeof o);
+        o.kind = OP_U2G;
+        o.sub = x.sub;
+        o.r0 = f.r0 << 6 | f.r1 << 4 | y.r0 << 2 | y.r1;
+        o.acc = -1;
+        if (f.flags & F_GRAD) g.acc[0] = f.acc;
+        if (y.flags & F_GRAD) g.acc[1] = y.acc;
+        if ((f.flags | y.flags) & F_GRAD) o.flags |= F_GRAD;
+        o.aux = (int)P.dgroup.size();
+        P.dgroup.push_back(g);
+        out.push_back(o);
+        i += 2;
+        continue;
+      }
+    }
+    out.push_back(P.dop[i++]);
+  }
+  P.dop.resize(begin);
+  P.dop.insert(P.dop.end(), out.begin(), out.end());
+}
+
 static std::string schedule(Plan &P, int K) {
   const int n = P.n;
   P.passes.clear();
@@ -1206,6 +1253,7 @@ static std::string emit(Plan &P) {
       for (int j : stage_ops) emit_op(P.ops[po[j]], po[j], S);
       if (!emit_error.empty()) return emit_error;
       group_u1(P, st.op_begin);
+      group_u2(P, st.op_begin);
       st.op_end = (int)P.dop.size();
       P.dstage.push_back(st);
       prev_regs = S;
@@ -1359,7 +1407,7 @@ std::string describe_plan(const Plan &P) {
           nu1 += __builtin_popcount((unsigned)P.dop[oi].r0);
           ++ngrp;
         }
-        nu2 += k == OP_U2;
+        nu2 += (k == OP_U2) + 2 * (k == OP_U2G);
         ndg += k == OP_DIAG;
         npm += k == OP_PERM;
         ndense += k == OP_DENSE;

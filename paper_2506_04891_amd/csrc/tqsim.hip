@@ -331,6 +331,10 @@ tqs_status launch_pass(tqs_circuit *c, int pi, int B, const cplx<T> *src0, cplx<
       for (int oi = P.dstage[st].op_begin; oi < P.dstage[st].op_end; ++oi) {
         if (P.dop[oi].kind == OP_DENSE) {
           f += (BWD ? 2.0 : 1.0) * dense_flops(P.nv);
+        } else if (P.dop[oi].kind == OP_U2G) {
+          // two structured pair gates (6 flop/amp each); MS gradients 8 each
+          const DevGroup &g = P.dgroup[P.dop[oi].aux];
+          for (int r = 0; r < 2; ++r) f += BWD ? 12.0 + (g.acc[r] >= 0 ? 8.0 : 0.0) : 6.0;
         } else if (P.dop[oi].kind == OP_U1G) {
           // each member: a complex 2x2 (14 flop/amp), backward twice that plus
           // its Pauli sums when it has parameters
