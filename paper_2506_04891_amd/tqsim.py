@@ -253,7 +253,9 @@ class Circuit:
 
 class QCircuitFn(torch.autograd.Function):
     """<Z_i> of a circuit, differentiable in weights and features by the adjoint
-    method (the final state is kept for backward; no intermediate states)."""
+    method.  Only the final state is kept for backward (no intermediate
+    states); the adjoint sweep uncomputes it, so a second backward through the
+    same graph (retain_graph, gradcheck) recomputes the forward state first."""
 
     @staticmethod
     def forward(ctx, circ, weights, features):
@@ -267,11 +269,13 @@ class QCircuitFn(torch.autograd.Function):
     @staticmethod
     def backward(ctx, g):
         weights, features = ctx.saved_tensors
-        if ctx.state is None:
-            raise RuntimeError("QCircuitFn.backward consumes the saved state; it can run only once")
-        gw, gx = ctx.circ.adjoint_grad(weights, features, ctx.state, g.contiguous())
+        state = ctx.state if ctx.state is not None else ctx.circ.forward(weights, features)
         ctx.state = None
-        return None, gw.to(weights.dtype), gx.to(features.dtype)
+        want_x = ctx.needs_input_grad[2]
+        gw, gx = ctx.circ.adjoint_grad(weights, features, state, g.contiguous(), want_features=want_x)
+        gw = gw.to(weights.dtype) if ctx.needs_input_grad[1] else None
+        gx = gx.to(features.dtype) if want_x else None
+        return None, gw, gx
 
 
 def expval(circ, weights, features):
