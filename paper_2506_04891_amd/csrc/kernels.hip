@@ -780,16 +780,84 @@ __device__ __forceinline__ void u1g_apply(cplx<T> (&v)[NREG], const cplx<T> (&m)
   if (MASK & 8) u1_apply<T, 3, ADJ>(v, m[3]);
 }
 
-template <typename T, bool ADJ>
-__device__ __forceinline__ void u1g_dispatch(cplx<T> (&v)[NREG], const cplx<T> (&m)[RB][4], int mask) {
+// Two structured gates of one kind on disjoint register-bit pairs (a,b), (c,d),
+// the pair holding bit 0 first; key = a<<6 | b<<4 | c<<2 | d.
+#define TQS_U2G_CASES(X)                                                                      \
+  X(0, 1, 2, 3) X(0, 1, 3, 2) X(1, 0, 2, 3) X(1, 0, 3, 2) X(0, 2, 1, 3) X(0, 2, 3, 1) X(2, 0, 1, 3) \
+  X(2, 0, 3, 1) X(0, 3, 1, 2) X(0, 3, 2, 1) X(3, 0, 1, 2) X(3, 0, 2, 1)
+
+// One grouped op in one piece of straight-line code: in the backward pass the
+// gradient sums at the group output, then the inverse gates on psi and lambda
+// (fewer merge points in the op loop, so fewer register copies).
+template <typename T, int K, bool BWD, int MASK>
+__device__ __forceinline__ void u1g_step(const Ctx<T, K> &c, const PassArgs<T> &a, cplx<T> (&vp)[NREG],
+                                         cplx<T> (&vl)[NREG], const cplx<T> (&m)[RB][4], const int (&ga)[RB]) {
+  if (BWD) {
+#pragma unroll
+    for (int r = 0; r < RB; ++r) {
+      if (!((MASK >> r) & 1) || ga[r] < 0) continue;
+      T sx = 0, sy = 0, sz = 0;
+      if (r == 0) u1_grad<T, 0>(vp, vl, sx, sy, sz);
+      if (r == 1) u1_grad<T, 1>(vp, vl, sx, sy, sz);
+      if (r == 2) u1_grad<T, 2>(vp, vl, sx, sy, sz);
+      if (r == 3) u1_grad<T, 3>(vp, vl, sx, sy, sz);
+      write_acc(c, a, sx, ga[r] + 0);
+      write_acc(c, a, sy, ga[r] + 1);
+      write_acc(c, a, sz, ga[r] + 2);
+    }
+  }
+  u1g_apply<T, MASK, BWD>(vp, m);
+  if (BWD) u1g_apply<T, MASK, true>(vl, m);
+}
+
+template <typename T, int K, bool BWD>
+__device__ __forceinline__ void u1g_run(const Ctx<T, K> &c, const PassArgs<T> &a, cplx<T> (&vp)[NREG],
+                                        cplx<T> (&vl)[NREG], const cplx<T> (&m)[RB][4], const int (&ga)[RB],
+                                        int mask) {
   switch (mask) {
 #define X(k) \
-  case k: { TQS_CASE_MARK(g##k); u1g_apply<T, k, ADJ>(v, m); TQS_CASE_MARK(eg##k); break; }
+  case k: { TQS_CASE_MARK(G##k); u1g_step<T, K, BWD, k>(c, a, vp, vl, m, ga); TQS_CASE_MARK(eG##k); break; }
     X(3) X(5) X(6) X(7) X(9) X(10) X(11) X(12) X(13) X(14) X(15)
 #undef X
     default: break;
   }
 }
+
+template <typename T, int K, bool BWD, int KIND, int A, int B, int C, int D>
+__device__ __forceinline__ void u2g_step(const Ctx<T, K> &c, const PassArgs<T> &a, cplx<T> (&vp)[NREG],
+                                         cplx<T> (&vl)[NREG], kptr<cplx<T>> m0, kptr<cplx<T>> m1, int a0,
+                                         int a1) {
+  if (BWD && KIND == U2_MS) {
+    if (a0 >= 0) write_acc(c, a, u2s_grad<T, A, B, true>(vp, vl), a0);
+    if (a1 >= 0) write_acc(c, a, u2s_grad<T, C, D, true>(vp, vl), a1);
+  }
+  u2s_apply<T, A, B, BWD, KIND>(vp, m0);
+  u2s_apply<T, C, D, BWD, KIND>(vp, m1);
+  if (BWD) {
+    u2s_apply<T, A, B, true, KIND>(vl, m0);
+    u2s_apply<T, C, D, true, KIND>(vl, m1);
+  }
+}
+
+template <typename T, int K, bool BWD, int KIND>
+__device__ __forceinline__ void u2g_run_k(const Ctx<T, K> &c, const PassArgs<T> &a, cplx<T> (&vp)[NREG],
+                                          cplx<T> (&vl)[NREG], kptr<cplx<T>> m0, kptr<cplx<T>> m1, int a0,
+                                          int a1, int key) {
+  switch (key) {
+#define X(p, q, r, t)                                                                          \
+  case (p << 6 | q << 4 | r << 2 | t): {                                                      \
+    TQS_CASE_MARK(H##p##q##r##t##_##KIND);                                                    \
+    u2g_step<T, K, BWD, KIND, p, q, r, t>(c, a, vp, vl, m0, m1, a0, a1);                       \
+    TQS_CASE_MARK(eH##p##q##r##t##_##KIND);                                                   \
+    break;                                                                                    \
+  }
+    TQS_U2G_CASES(X)
+#undef X
+    default: break;
+  }
+}
+
+
 
 template <typename T>
 __device__ __forceinline__ void u1_grad_dispatch(const cplx<T> (&p)[NREG], const cplx<T> (&l)[NREG],
@@ -838,56 +906,6 @@ __device__ __forceinline__ void u2_apply_any(cplx<T> (&v)[NREG], kptr<cplx<T>> m
   }
 }
 
-// Two structured gates of one kind on disjoint register-bit pairs (a,b), (c,d),
-// the pair holding bit 0 first; key = a<<6 | b<<4 | c<<2 | d.
-#define TQS_U2G_CASES(X)                                                                      \
-  X(0, 1, 2, 3) X(0, 1, 3, 2) X(1, 0, 2, 3) X(1, 0, 3, 2) X(0, 2, 1, 3) X(0, 2, 3, 1) X(2, 0, 1, 3) \
-  X(2, 0, 3, 1) X(0, 3, 1, 2) X(0, 3, 2, 1) X(3, 0, 1, 2) X(3, 0, 2, 1)
-
-template <typename T, bool ADJ, int KIND>
-__device__ __forceinline__ void u2g_dispatch_k(cplx<T> (&v)[NREG], kptr<cplx<T>> m0, kptr<cplx<T>> m1, int key) {
-  switch (key) {
-#define X(a, b, c, d)                                                                    \
-  case (a << 6 | b << 4 | c << 2 | d): {                                                 \
-    TQS_CASE_MARK(h##a##b##c##d##_##KIND);                                               \
-    u2s_apply<T, a, b, ADJ, KIND>(v, m0);                                                \
-    u2s_apply<T, c, d, ADJ, KIND>(v, m1);                                                \
-    TQS_CASE_MARK(eh##a##b##c##d##_##KIND);                                              \
-    break;                                                                               \
-  }
-    TQS_U2G_CASES(X)
-#undef X
-    default: break;
-  }
-}
-
-template <typename T, bool ADJ>
-__device__ __forceinline__ void u2g_dispatch(cplx<T> (&v)[NREG], kptr<cplx<T>> m0, kptr<cplx<T>> m1, int key,
-                                             int sub) {
-  if (sub == U2_MS)
-    u2g_dispatch_k<T, ADJ, U2_MS>(v, m0, m1, key);
-  else
-    u2g_dispatch_k<T, ADJ, U2_ECR>(v, m0, m1, key);
-}
-
-// X(x)X sums of both pairs of a group, taken at the group's output.
-template <typename T>
-__device__ __forceinline__ void u2g_grad_xx(const cplx<T> (&p)[NREG], const cplx<T> (&l)[NREG], int key, T &g0,
-                                            T &g1) {
-  switch (key) {
-#define X(a, b, c, d)                                             \
-  case (a << 6 | b << 4 | c << 2 | d): {                          \
-    TQS_CASE_MARK(x##a##b##c##d);                                 \
-    g0 = u2s_grad<T, a, b, true>(p, l);                           \
-    g1 = u2s_grad<T, c, d, true>(p, l);                           \
-    TQS_CASE_MARK(ex##a##b##c##d);                                \
-    break;                                                        \
-  }
-    TQS_U2G_CASES(X)
-#undef X
-    default: g0 = g1 = T(0); break;
-  }
-}
 
 template <typename T, bool XX>
 __device__ __forceinline__ T u2s_grad_dispatch(const cplx<T> (&p)[NREG], const cplx<T> (&l)[NREG], int r0,
@@ -1210,45 +1228,27 @@ __device__ __forceinline__ void run_stage(const Ctx<T, K> &c, const PassArgs<T> 
         if (BWD) u1_dispatch<T, true>(vl, m, op.r0, op.flags);
       }
     } else if (op.kind == OP_U1G) {
+      // the members commute, so every gradient is taken at the group's output
       kptr<DevGroup> gp = a.groups + op.aux;
       cplx<T> m[RB][4];
+      int ga[RB];
 #pragma unroll
       for (int r = 0; r < RB; ++r) {
         const int mo = uni(gp->mat[r]);
+        ga[r] = (op.flags & F_GRAD) ? uni(gp->acc[r]) : -1;
         kptr<cplx<T>> ms = a.mats + (mo < 0 ? 0 : mo);
 #pragma unroll
         for (int q = 0; q < 4; ++q) m[r][q] = kld(ms, q);
       }
-      if (BWD && (op.flags & F_GRAD)) {
-        // the members commute, so every gradient is taken at the group's output
-#pragma unroll
-        for (int r = 0; r < RB; ++r) {
-          const int ga = uni(gp->acc[r]);
-          if (ga < 0) continue;
-          T sx = 0, sy = 0, sz = 0;
-          if (r == 0) u1_grad<T, 0>(vp, vl, sx, sy, sz);
-          if (r == 1) u1_grad<T, 1>(vp, vl, sx, sy, sz);
-          if (r == 2) u1_grad<T, 2>(vp, vl, sx, sy, sz);
-          if (r == 3) u1_grad<T, 3>(vp, vl, sx, sy, sz);
-          write_acc(c, a, sx, ga + 0);
-          write_acc(c, a, sy, ga + 1);
-          write_acc(c, a, sz, ga + 2);
-        }
-      }
-      u1g_dispatch<T, BWD>(vp, m, op.r0);
-      if (BWD) u1g_dispatch<T, true>(vl, m, op.r0);
+      u1g_run<T, K, BWD>(c, a, vp, vl, m, ga, op.r0);
     } else if (op.kind == OP_U2G) {
       kptr<DevGroup> gp = a.groups + op.aux;
       kptr<cplx<T>> m0 = a.mats + uni(gp->mat[0]), m1 = a.mats + uni(gp->mat[1]);
-      if (BWD && (op.flags & F_GRAD)) {
-        T g0, g1;
-        u2g_grad_xx(vp, vl, op.r0, g0, g1);
-        const int a0 = uni(gp->acc[0]), a1 = uni(gp->acc[1]);
-        if (a0 >= 0) write_acc(c, a, g0, a0);
-        if (a1 >= 0) write_acc(c, a, g1, a1);
-      }
-      u2g_dispatch<T, BWD>(vp, m0, m1, op.r0, op.sub);
-      if (BWD) u2g_dispatch<T, true>(vl, m0, m1, op.r0, op.sub);
+      const int a0 = (op.flags & F_GRAD) ? uni(gp->acc[0]) : -1, a1 = (op.flags & F_GRAD) ? uni(gp->acc[1]) : -1;
+      if (op.sub == U2_MS)
+        u2g_run_k<T, K, BWD, U2_MS>(c, a, vp, vl, m0, m1, a0, a1, op.r0);
+      else
+        u2g_run_k<T, K, BWD, U2_ECR>(c, a, vp, vl, m0, m1, a0, a1, op.r0);
     } else if (op.kind == OP_U2) {
       kptr<cplx<T>> mg = op_mat(a, op, s_thr);
       if (BWD && (op.flags & F_GRAD)) {
