@@ -332,6 +332,12 @@ static std::string build_ir(Plan &P, const std::vector<Inst> &insts) {
 
   std::vector<int> open_u1(n, -1);
   int cur_layer = -1, layer_diag = -1, layer_perm = -1, gpi_diag = -1, gpi_perm = -1;
+  // CNOT / SWAP gates after the last other gate of the circuit: they only
+  // permute the final state, so they all become one index map, which the last
+  // pass applies as it stores (no pass of their own)
+  size_t trailing_from = 0;
+  for (size_t i = 0; i < insts.size(); ++i)
+    if (!consumed[i] && insts[i].gate != CNOT && insts[i].gate != SWAP) trailing_from = i + 1;
   for (size_t i = 0; i < insts.size(); ++i) {
     if (consumed[i]) continue;
     if (P.dense) {
@@ -441,7 +447,7 @@ static std::string build_ir(Plan &P, const std::vector<Inst> &insts) {
       layer_perm = -1;
     } else if ((g == CNOT || g == SWAP) && !P.resident) {
       const bool down = (g == CNOT) && (B.bit(in.w0) > B.bit(in.w1));
-      if (!fused || down) {
+      if (!fused || down || i >= trailing_from) {
         if (!(layer_perm >= 0 && layer_perm == (int)P.ops.size() - 1)) layer_perm = B.new_op(IR_PERM);
         P.ops[layer_perm].F = B.perm_of(g, in.w0, in.w1).after(P.ops[layer_perm].F);
       } else {
