@@ -1324,8 +1324,17 @@ __device__ __forceinline__ void run_stage(const Ctx<T, K> &c, const PassArgs<T> 
   __syncthreads();
 }
 
+// Occupancy targets for single precision: forward 3 waves per SIMD (at most
+// 168 registers), backward 2 (at most 256, shared by the architectural and
+// accumulation registers).
+template <typename T, bool BWD>
+struct PassOcc {
+  static constexpr int waves = (sizeof(T) == 4 && !BWD) ? 3 : (sizeof(T) == 4 ? 2 : 1);
+};
+
 template <typename T, int K, bool BWD, bool DENSE>
-__global__ void __launch_bounds__(1 << (K - RB)) k_pass(PassArgs<T> a) {
+__global__ void __launch_bounds__(1 << (K - RB))
+__attribute__((amdgpu_waves_per_eu(PassOcc<T, BWD>::waves))) k_pass(PassArgs<T> a) {
   constexpr int NT = 1 << (K - RB);
   constexpr int NE = 1 << K;
   extern __shared__ __align__(16) unsigned char smem[];
@@ -1460,37 +1469,70 @@ __global__ void __launch_bounds__(1 << (K - RB)) k_pass(PassArgs<T> a) {
       }
     }
   } else if (fwd_load_global || BWD) {
+    // every element of the thread is requested before any is waited for:
+    // the tile's loads are in flight together (one memory latency per tile)
+    cplx<T> tp[NREG], tl[NREG];
+    if (!c.multi) {
+      uint32_t kk[NREG];
+      if (lmap) {
 #pragma unroll
-    for (int i = 0; i < NREG; ++i) {
-      const int t = c.tid + i * NT;
-      cplx<T> vp = cmk<T>(0, 0), vl = cmk<T>(0, 0);
-      if (!c.multi) {
-        uint32_t k;
-        if (lmap) {
-          k = lbase ^ lthr;
+        for (int i = 0; i < NREG; ++i) {
+          uint32_t k = lbase ^ lthr;
 #pragma unroll
           for (int b = 0; b < RB; ++b)
             if ((i >> b) & 1) k ^= lreg[b];
-        } else {
-          k = c.base | ptid;
+          kk[i] = k;
+        }
+      } else {
+#pragma unroll
+        for (int i = 0; i < NREG; ++i) {
+          uint32_t k = c.base | ptid;
 #pragma unroll
           for (int b = 0; b < RB; ++b)
             if ((i >> b) & 1) k |= treg[b];
-        }
-        const long long g = (long long)c.sample0 * sstride + k;
-        vp = a.src0[g];
-        if (BWD) vl = a.src1[g];
-      } else {
-        const int s = c.sample0 + (t >> c.nv);
-        const int j = t & ((1 << c.nv) - 1);
-        if (s < a.batch && j < (1 << n)) {
-          const long long g = (long long)s * sstride + j;
-          vp = a.src0[g];
-          if (BWD) vl = a.src1[g];
+          kk[i] = k;
         }
       }
-      Lp[swz<T>(t)] = vp;
-      if (BWD) Ll[swz<T>(t)] = vl;
+      const cplx<T> *s0 = a.src0 + (long long)c.sample0 * sstride;
+#pragma unroll
+      for (int i = 0; i < NREG; ++i) tp[i] = s0[kk[i]];
+      if (BWD) {
+        const cplx<T> *s1 = a.src1 + (long long)c.sample0 * sstride;
+#pragma unroll
+        for (int i = 0; i < NREG; ++i) tl[i] = s1[kk[i]];
+      }
+    } else {
+      // several samples per workgroup: elements past the batch or the state
+      // (virtual padding) read element 0 and are replaced by zero
+      long long gg[NREG];
+      bool ok[NREG];
+#pragma unroll
+      for (int i = 0; i < NREG; ++i) {
+        const int t = c.tid + i * NT;
+        const int smp = c.sample0 + (t >> c.nv);
+        const int j = t & ((1 << c.nv) - 1);
+        ok[i] = smp < a.batch && j < (1 << n);
+        gg[i] = ok[i] ? (long long)smp * sstride + j : 0;
+      }
+#pragma unroll
+      for (int i = 0; i < NREG; ++i) tp[i] = a.src0[gg[i]];
+      if (BWD) {
+#pragma unroll
+        for (int i = 0; i < NREG; ++i) tl[i] = a.src1[gg[i]];
+      }
+#pragma unroll
+      for (int i = 0; i < NREG; ++i) {
+        if (!ok[i]) {
+          tp[i] = cmk<T>(0, 0);
+          tl[i] = cmk<T>(0, 0);
+        }
+      }
+    }
+#pragma unroll
+    for (int i = 0; i < NREG; ++i) {
+      const int t = c.tid + i * NT;
+      Lp[swz<T>(t)] = tp[i];
+      if (BWD) Ll[swz<T>(t)] = tl[i];
     }
   }
   __syncthreads();
@@ -1511,35 +1553,56 @@ __global__ void __launch_bounds__(1 << (K - RB)) k_pass(PassArgs<T> a) {
   }
 
   // ---------------- store ----------------
+  // an opaque copy of the thread's index bits: otherwise the compiler keeps the
+  // load phase's element indices alive through every stage to reuse them here
+  uint32_t ptid_s = ptid;
+  asm volatile("" : "+v"(ptid_s));
+  cplx<T> tp[NREG], tl[NREG];
 #pragma unroll
   for (int i = 0; i < NREG; ++i) {
     const int t = c.tid + i * NT;
-    const cplx<T> vp = Lp[swz<T>(t)];
-    cplx<T> vl;
-    if (BWD) vl = Ll[swz<T>(t)];
-    if (!c.multi) {
-      uint32_t k;
-      if (smap) {
-        k = sbase ^ sthr;
+    tp[i] = Lp[swz<T>(t)];
+    if (BWD) tl[i] = Ll[swz<T>(t)];
+  }
+  if (!c.multi) {
+    uint32_t kk[NREG];
+    if (smap) {
+#pragma unroll
+      for (int i = 0; i < NREG; ++i) {
+        uint32_t k = sbase ^ sthr;
 #pragma unroll
         for (int b = 0; b < RB; ++b)
           if ((i >> b) & 1) k ^= sreg[b];
-      } else {
-        k = c.base | ptid;
+        kk[i] = k;
+      }
+    } else {
+#pragma unroll
+      for (int i = 0; i < NREG; ++i) {
+        uint32_t k = c.base | ptid_s;
 #pragma unroll
         for (int b = 0; b < RB; ++b)
           if ((i >> b) & 1) k |= treg[b];
+        kk[i] = k;
       }
-      const long long g = (long long)c.sample0 * sstride + k;
-      a.dst0[g] = vp;
-      if (BWD) a.dst1[g] = vl;
-    } else {
-      const int s = c.sample0 + (t >> c.nv);
+    }
+    cplx<T> *d0 = a.dst0 + (long long)c.sample0 * sstride;
+#pragma unroll
+    for (int i = 0; i < NREG; ++i) d0[kk[i]] = tp[i];
+    if (BWD) {
+      cplx<T> *d1 = a.dst1 + (long long)c.sample0 * sstride;
+#pragma unroll
+      for (int i = 0; i < NREG; ++i) d1[kk[i]] = tl[i];
+    }
+  } else {
+#pragma unroll
+    for (int i = 0; i < NREG; ++i) {
+      const int t = c.tid + i * NT;
+      const int smp = c.sample0 + (t >> c.nv);
       const int j = t & ((1 << c.nv) - 1);
-      if (s < a.batch && j < (1 << n)) {
-        const long long g = (long long)s * sstride + j;
-        a.dst0[g] = vp;
-        if (BWD) a.dst1[g] = vl;
+      if (smp < a.batch && j < (1 << n)) {
+        const long long g = (long long)smp * sstride + j;
+        a.dst0[g] = tp[i];
+        if (BWD) a.dst1[g] = tl[i];
       }
     }
   }
@@ -1617,15 +1680,20 @@ __global__ void __launch_bounds__(NTE) k_expval(ReadArgs<T> a) {
   double sr[RB];
 #pragma unroll
   for (int b = 0; b < RB; ++b) sr[b] = 0.0;
+  long long gi[NREG];
+  bool ok[NREG];
+  cplx<T> v[NREG];
 #pragma unroll
   for (int i = 0; i < NREG; ++i) {
-    long long g;
-    double p = 0.0;
     const int t = COAL ? tid + i * NTE : tid * NREG + i;
-    if (rd_elem(c, n, a.batch, t, g)) {
-      const cplx<T> v = a.psi[g];
-      p = (double)v.x * (double)v.x + (double)v.y * (double)v.y;
-    }
+    ok[i] = rd_elem(c, n, a.batch, t, gi[i]);
+    if (!ok[i]) gi[i] = 0;
+  }
+#pragma unroll
+  for (int i = 0; i < NREG; ++i) v[i] = a.psi[gi[i]];
+#pragma unroll
+  for (int i = 0; i < NREG; ++i) {
+    const double p = ok[i] ? (double)v[i].x * (double)v[i].x + (double)v[i].y * (double)v[i].y : 0.0;
     tot += p;
 #pragma unroll
     for (int b = 0; b < RB; ++b) sr[b] += ((i >> b) & 1) ? -p : p;
@@ -1726,19 +1794,27 @@ __global__ void __launch_bounds__(NTE) k_adj_init(ReadArgs<T> a) {
     if (p >= RB0 && p < RB0 + RB) continue;
     hthr += ((j0 >> p) & 1) ? -gg[n - 1 - p] : gg[n - 1 - p];
   }
+  // all loads first (one memory latency per thread), then the products
+  long long gi[NREG];
+  bool ok[NREG];
+  cplx<T> v[NREG];
 #pragma unroll
   for (int i = 0; i < NREG; ++i) {
-    long long g;
     const int t = COAL ? tid + i * NTE : tid * NREG + i;
-    if (!rd_elem(c, n, a.batch, t, g)) continue;
+    ok[i] = rd_elem(c, n, a.batch, t, gi[i]);
+    if (!ok[i]) gi[i] = g0;
+  }
+#pragma unroll
+  for (int i = 0; i < NREG; ++i) v[i] = a.psi[gi[i]];
+#pragma unroll
+  for (int i = 0; i < NREG; ++i) {
     double h = hthr;
 #pragma unroll
     for (int b = 0; b < RB; ++b) {
       const int p = RB0 + b;
       if (p < n) h += ((i >> b) & 1) ? -gg[n - 1 - p] : gg[n - 1 - p];
     }
-    const cplx<T> v = a.psi[g];
-    a.lam[g] = cmk<T>((T)(v.x * h), (T)(v.y * h));
+    if (ok[i]) a.lam[gi[i]] = cmk<T>((T)(v[i].x * h), (T)(v[i].y * h));
   }
 }
 
