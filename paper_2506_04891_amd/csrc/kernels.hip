@@ -1324,17 +1324,18 @@ __device__ __forceinline__ void run_stage(const Ctx<T, K> &c, const PassArgs<T> 
   __syncthreads();
 }
 
-// Occupancy targets for single precision: forward 3 waves per SIMD (at most
-// 168 registers), backward 2 (at most 256, shared by the architectural and
-// accumulation registers).
-template <typename T, bool BWD>
+// Occupancy targets of the single-precision tile passes: forward 3 waves per
+// SIMD (at most 168 registers), backward 2 (at most 256, shared by the
+// architectural and accumulation registers).  Double precision and the
+// matrix-core variant are left to the compiler.
+template <typename T, bool BWD, bool DENSE>
 struct PassOcc {
-  static constexpr int waves = (sizeof(T) == 4 && !BWD) ? 3 : (sizeof(T) == 4 ? 2 : 1);
+  static constexpr int waves = (sizeof(T) != 4 || DENSE) ? 1 : (BWD ? 2 : 3);
 };
 
 template <typename T, int K, bool BWD, bool DENSE>
 __global__ void __launch_bounds__(1 << (K - RB))
-__attribute__((amdgpu_waves_per_eu(PassOcc<T, BWD>::waves))) k_pass(PassArgs<T> a) {
+__attribute__((amdgpu_waves_per_eu(PassOcc<T, BWD, DENSE>::waves))) k_pass(PassArgs<T> a) {
   constexpr int NT = 1 << (K - RB);
   constexpr int NE = 1 << K;
   extern __shared__ __align__(16) unsigned char smem[];

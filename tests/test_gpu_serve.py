@@ -79,3 +79,23 @@ def test_graph_replays_equal_eager():
         np.testing.assert_allclose(o.expz, e, atol=2e-5)
         np.testing.assert_allclose(o.grad_weights, gw, rtol=1e-4, atol=1e-6)
     assert len(ex._graphs) >= 1
+
+
+def test_heavy_lane_large_requests_equal_alone():
+    """Large requests (up to 20 qubits) go through the heavy lane one at a time
+    while small ones pass them; every result equals the request run alone."""
+    reqs = _reqs(12, seed=21, n_range=(8, 20), b_max=16, blocks=(2, 3))
+    note(f"case serve heavy requests={len(reqs)} n={[r.n for r in reqs]}")
+    srv = Server(GpuExecutor(streams=4, graphs=True), budget_bytes=32 << 30, streams=4, paused=True,
+                 heavy_bytes=64 << 20)
+    futs = [srv.submit(r) for r in reqs]
+    srv.resume()
+    res = [f.result(timeout=120) for f in futs]
+    srv.close()
+    assert srv.max_heavy_inflight <= 1
+    for r, got in zip(reqs, res):
+        e, gw, gx = _alone(r)
+        np.testing.assert_allclose(got.expz, e, atol=2e-5)
+        if r.want_grad:
+            for a, b in ((got.grad_weights, gw), (got.grad_features, gx)):
+                assert np.max(np.abs(a - b)) <= 1e-4 * max(np.max(np.abs(b)), 1e-30)
