@@ -1,6 +1,7 @@
-"""Large states on the GPU (up to 2^26 amplitudes per sample, 64-bit global
-indexing, many workgroups per sample), checked against closed forms that hold
-at any size: after an RY(x) embedding and a CNOT ring,
+"""Large states on the GPU, up to 2^30 amplitudes per sample (the largest
+circuit the library accepts): 64-bit global indexing, many workgroups per
+sample.  Checked against closed forms that hold at any size: after an RY(x)
+embedding and a CNOT ring,
 <Z_k> = prod_{i<=k} cos x_i (k >= 1) and <Z_0> = prod_{i>=1} cos x_i; diagonal
 layers after the ring change no <Z_k>, so their weight gradients are zero."""
 import numpy as np
@@ -31,7 +32,7 @@ def _closed_form(x):
     return e, gx
 
 
-@pytest.mark.parametrize("n,B", [(26, 2), (24, 5), (21, 3)])
+@pytest.mark.parametrize("n,B", [(30, 1), (28, 2), (26, 2), (24, 5), (21, 3)])
 def test_large_state_closed_form(n, B):
     b = W._Builder(n)
     b.add("RY", "ALL", "INPUT").add("CNOT", "RING").add("RZ", "ALL", "WEIGHT").add("ZZ", "RING", "WEIGHT")
