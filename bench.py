@@ -247,9 +247,10 @@ def dense_sweep(iters=30):
                     print(json.dumps(row), flush=True)
 
 
-def _oracle_samples(samples, seed_offset=0):
+def _oracle_samples(samples, seed_offset=0, keep=None):
     """Seconds the oracle (numpy complex128, one BLAS thread) takes for forward
-    <Z_i> + adjoint gradients of `samples` rows of each 16-qubit circuit."""
+    <Z_i> + adjoint gradients of `samples` rows of each 16-qubit circuit.
+    keep: dict that receives {circuit: (rows, expz, grad_w, grad_x)}."""
     import numpy as np
     from threadpoolctl import threadpool_limits
     import workloads as W
@@ -262,8 +263,10 @@ def _oracle_samples(samples, seed_offset=0):
             xs = x[rows]
             g = W.upstream(samples, n, "ones")
             t0 = time.perf_counter()
-            sim.grad_adjoint(n, layers, w, xs, g)
+            res = sim.grad_adjoint(n, layers, w, xs, g)
             t += time.perf_counter() - t0
+            if keep is not None:
+                keep[name] = (rows, *res)
     return t
 
 
@@ -271,14 +274,39 @@ def _pool_worker(k, per_worker):
     return _oracle_samples(per_worker, seed_offset=k * per_worker)
 
 
-def cpu_baseline(sample=4):
+def cpu_baseline(sample=4, keep=None):
     """The oracle on `sample` rows of each 16-qubit circuit, one thread."""
-    t = _oracle_samples(sample)
+    t = _oracle_samples(sample, keep=keep)
     evals = 2 * sample
     return {"value": round(evals / t, 3), "unit": "circuit evals/s", "cores": 1, "kind": "oracle",
             "sample": f"{sample} rows of each 16-qubit circuit (IonQ and IBM gate sets), forward + adjoint "
                       f"gradients in numpy complex128 on one thread (BLAS limited to 1); {round(t, 2)} s; "
                       f"host has {os.cpu_count()} logical CPUs"}
+
+
+def errors_vs_oracle(jobs, ref):
+    """Max errors of the benchmarked GPU path against the oracle rows kept by
+    cpu_baseline: <Z_i> (max abs), weight and feature gradients (max abs over
+    max |ref|), with the upstream gradient one on those rows and zero elsewhere."""
+    import numpy as np
+    import torch
+    out = {}
+    for j in jobs:
+        if j.name not in ref:
+            continue
+        rows, e_ref, gw_ref, gx_ref = ref[j.name]
+        c = j.circ
+        c.forward(j.w, j.x, state=j.state, ws=j.ws)
+        e = c.expval_z(j.state, ws=j.ws).cpu().numpy()
+        g = torch.zeros_like(j.g)
+        g[rows] = 1.0
+        gw, gx = c.adjoint_grad(j.w, j.x, j.state, g, ws=j.ws)
+        gw, gx = gw.cpu().numpy(), gx.cpu().numpy()
+        out[j.name] = {"rows": rows,
+                       "expz_max_abs": float(np.max(np.abs(e[rows] - e_ref))),
+                       "grad_weights_max_rel": float(np.max(np.abs(gw - gw_ref)) / np.max(np.abs(gw_ref))),
+                       "grad_features_max_rel": float(np.max(np.abs(gx[rows] - gx_ref)) / np.max(np.abs(gx_ref)))}
+    return out
 
 
 def cpu_baseline_pool(per_worker=2):
@@ -304,7 +332,8 @@ def main():
         sys.exit(2)
     # the CPU baselines run first: the pooled one forks, which must happen
     # before anything initialises the GPU in this process
-    cpu = None if (a.no_cpu_baseline or a.dense_sweep) else cpu_baseline()
+    oracle_rows = {}
+    cpu = None if (a.no_cpu_baseline or a.dense_sweep) else cpu_baseline(keep=oracle_rows)
     cpu_pool = None if (a.no_cpu_baseline or a.dense_sweep) else cpu_baseline_pool()
     import torch
     if not torch.cuda.is_available():
@@ -340,6 +369,7 @@ def main():
                    "mode": a.mode, "passes": {j.name: len(j.circ.plan()["passes"]) for j in jobs}},
         "roofline": roofline(rep, traffic_file),
         "kernels": {k: {"count": v["count"], "ms_per_step": round(v["ms"] / a.steps, 4)} for k, v in rep.items()},
+        "errors_vs_oracle": errors_vs_oracle(jobs, oracle_rows),
     }
     if a.calibrate_copy_mib > 0:
         src = torch.ones(a.calibrate_copy_mib << 18, dtype=torch.float32, device="cuda")
