@@ -47,6 +47,9 @@ def parse():
     # each dispatch mode (tile passes per layer, fused tile passes, dense
     # matrix-core layers) and print one JSON line per case
     p.add_argument("--dense-sweep", action="store_true")
+    # instead of the benchmark: time every configuration under each dispatch
+    # mode and tile size, one JSON line per case
+    p.add_argument("--dispatch-sweep", action="store_true")
     return p.parse_args()
 
 
@@ -247,6 +250,45 @@ def dense_sweep(iters=30):
                     print(json.dumps(row), flush=True)
 
 
+def dispatch_sweep(iters=10):
+    """ms per forward + <Z> + adjoint step of each configuration under the
+    per-layer, fused and dense modes and tile sizes 10..12 (0 = automatic)."""
+    import torch
+    import workloads as W
+    from paper_2506_04891_amd import tqsim as T
+    dev = torch.device("cuda")
+    for name in ("c1_4q_b16", "c2_12q_b256", "c4a_16q_b128_ionq", "c4b_16q_b128_ibm", "c3_20q_b32"):
+        n, B, dt, layers, w, x = W.config(name)
+        for mode in ("auto", "per_layer", "fused", "dense"):
+            for K in ((0,) if mode in ("auto", "dense") else (0, 10, 11, 12)):
+                if mode == "dense" and n > 6:
+                    continue
+                c = T.Circuit(n, layers, dt, mode=mode, tile_bits=K)
+                wt, xt = torch.tensor(w, device=dev), torch.tensor(x, device=dev)
+                g = torch.ones((B, n), dtype=torch.float64, device=dev)
+                st = torch.empty((B, 2 ** n), dtype=c.complex_dtype, device=dev)
+                ws = c.workspace(B, True, dev)
+
+                def step():
+                    c.forward(wt, xt, state=st, ws=ws)
+                    c.expval_z(st, ws=ws)
+                    c.adjoint_grad(wt, xt, st, g, ws=ws)
+                for _ in range(3):
+                    step()
+                torch.cuda.synchronize()
+                e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                e0.record()
+                for _ in range(iters):
+                    step()
+                e1.record()
+                torch.cuda.synchronize()
+                ms = e0.elapsed_time(e1) / iters
+                plan = c.plan()
+                print(json.dumps({"config": name, "mode": mode, "tile_bits": K, "plan_mode": plan["mode"],
+                                  "passes": len(plan["passes"]), "ms_per_step": round(ms, 4),
+                                  "evals_per_s": round(B / ms * 1e3, 1)}), flush=True)
+
+
 def _oracle_samples(samples, seed_offset=0, keep=None):
     """Seconds the oracle (numpy complex128, one BLAS thread) takes for forward
     <Z_i> + adjoint gradients of `samples` rows of each 16-qubit circuit.
@@ -333,8 +375,9 @@ def main():
     # the CPU baselines run first: the pooled one forks, which must happen
     # before anything initialises the GPU in this process
     oracle_rows = {}
-    cpu = None if (a.no_cpu_baseline or a.dense_sweep) else cpu_baseline(keep=oracle_rows)
-    cpu_pool = None if (a.no_cpu_baseline or a.dense_sweep) else cpu_baseline_pool()
+    sweep = a.dense_sweep or a.dispatch_sweep
+    cpu = None if (a.no_cpu_baseline or sweep) else cpu_baseline(keep=oracle_rows)
+    cpu_pool = None if (a.no_cpu_baseline or sweep) else cpu_baseline_pool()
     import torch
     if not torch.cuda.is_available():
         print(json.dumps({"error": "no GPU visible"}))
@@ -343,6 +386,9 @@ def main():
     T.lib()   # fails loudly when the HIP library is missing
     if a.dense_sweep:
         dense_sweep()
+        return
+    if a.dispatch_sweep:
+        dispatch_sweep()
         return
 
     jobs = [Job("c4a_16q_b128_ionq", a.mode), Job("c4b_16q_b128_ibm", a.mode)]
