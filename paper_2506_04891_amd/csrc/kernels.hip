@@ -659,6 +659,10 @@ struct PassArgs {
   long long acc_region;   // first partial of this pass
   int units;              // partial units per sample of this pass
   int batch;
+  // first backward pass: lambda = (sum_i g_i Z_i) psi is formed from psi as the
+  // tile is loaded (no separate adjoint-init kernel, no lambda read); g [B, n]
+  const double *g;
+  int init_lambda;
 };
 
 template <typename T>
@@ -1497,7 +1501,37 @@ __attribute__((amdgpu_waves_per_eu(PassOcc<T, BWD, DENSE>::waves))) k_pass(PassA
       const cplx<T> *s0 = a.src0 + (long long)c.sample0 * sstride;
 #pragma unroll
       for (int i = 0; i < NREG; ++i) tp[i] = s0[kk[i]];
-      if (BWD) {
+      if (BWD && uni(a.init_lambda)) {
+        // lambda_k = psi_k * h(k), h(k) = sum_p g[n-1-p] (-1)^{bit p of k}.  The
+        // element index is k_i = T0 ^ (xor of the columns selected by i), so h
+        // is the 16-point Walsh-Hadamard transform of the weights grouped by
+        // the pattern of bit p across the four columns.
+        const uint32_t T0 = lmap ? (lbase ^ lthr) : (c.base | ptid);
+        uint32_t col[RB];
+#pragma unroll
+        for (int b = 0; b < RB; ++b) col[b] = lmap ? lreg[b] : treg[b];
+        kptr<double> gs = kc(a.g) + (long long)c.sample0 * n;
+        double H[NREG];
+#pragma unroll
+        for (int q = 0; q < NREG; ++q) H[q] = 0.0;
+        for (int p = 0; p < n; ++p) {
+          const double wp = gs[n - 1 - p];
+          const double v = ((T0 >> p) & 1) ? -wp : wp;
+          int cp = 0;
+#pragma unroll
+          for (int b = 0; b < RB; ++b) cp |= (int)((col[b] >> p) & 1) << b;
+          switch (uni(cp)) {
+#define X(q) \
+  case q: H[q] += v; break;
+            X(0) X(1) X(2) X(3) X(4) X(5) X(6) X(7) X(8) X(9) X(10) X(11) X(12) X(13) X(14) X(15)
+#undef X
+          }
+        }
+        wht16(H);
+#pragma unroll
+        for (int i = 0; i < NREG; ++i)
+          tl[i] = cmk<T>((T)((double)tp[i].x * H[i]), (T)((double)tp[i].y * H[i]));
+      } else if (BWD) {
         const cplx<T> *s1 = a.src1 + (long long)c.sample0 * sstride;
 #pragma unroll
         for (int i = 0; i < NREG; ++i) tl[i] = s1[kk[i]];

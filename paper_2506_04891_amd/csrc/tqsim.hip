@@ -291,7 +291,7 @@ void launch_pass_k(const PassArgs<T> &a, int grid, size_t lds, hipStream_t s) {
 template <typename T, bool BWD>
 tqs_status launch_pass(tqs_circuit *c, int pi, int B, const cplx<T> *src0, cplx<T> *dst0,
                        const cplx<T> *src1, cplx<T> *dst1, char *ws, const WsLayout &L,
-                       hipStream_t s) {
+                       hipStream_t s, const double *g_init = nullptr) {
   const Plan &P = c->plan;
   const DevPass &d = P.dpass[pi];
   PassArgs<T> a;
@@ -316,6 +316,8 @@ tqs_status launch_pass(tqs_circuit *c, int pi, int B, const cplx<T> *src0, cplx<
   a.acc_region = (long long)B * P.pass_prefix[pi];
   a.units = P.pass_units[pi];
   a.batch = B;
+  a.g = g_init;
+  a.init_lambda = g_init != nullptr;
   const int grid = pass_grid(d, B);
   const size_t es = sizeof(cplx<T>);
   const size_t lds = ((size_t)(BWD ? 2 : 1) * ((size_t)1 << d.K) + (size_t)d.diag_lds) * es;
@@ -323,7 +325,7 @@ tqs_status launch_pass(tqs_circuit *c, int pi, int B, const cplx<T> *src0, cplx<
   if (c->profile) {
     const double amps = (double)B * (double)(1ll << P.n);
     if (BWD)
-      bytes = amps * es * (2.0 + (d.skip_bwd_store ? 0.0 : 2.0));
+      bytes = amps * es * ((g_init ? 1.0 : 2.0) + (d.skip_bwd_store ? 0.0 : 2.0));
     else
       bytes = amps * es * ((d.load_mode == LOAD_GLOBAL ? 1.0 : 0.0) + 1.0);
     double f = 0;
@@ -466,7 +468,11 @@ tqs_status adjoint_t(tqs_circuit *c, int B, const double *w, const double *x, vo
   cplx<T> *X = L.has_x ? reinterpret_cast<cplx<T> *>(ws + L.x) : nullptr;
   cplx<T> *LA = reinterpret_cast<cplx<T> *>(ws + L.la);
   cplx<T> *LB = L.has_lb ? reinterpret_cast<cplx<T> *>(ws + L.lb) : nullptr;
-  {
+  // when the first backward pass holds one sample per workgroup it forms
+  // lambda itself as it loads psi; otherwise a separate kernel does
+  const int last = (int)P.passes.size() - 1;
+  const bool fused_init = P.nv > P.dpass[last].K;
+  if (!fused_init) {
     ReadArgs<T> a;
     a.psi = S;
     a.lam = LA;
@@ -494,7 +500,7 @@ tqs_status adjoint_t(tqs_circuit *c, int B, const double *w, const double *x, vo
       pd = (pc == S) ? X : S;
       ld = (lc == LA) ? LB : LA;
     }
-    st = launch_pass<T, true>(c, p, B, pc, pd, lc, ld, ws, L, s);
+    st = launch_pass<T, true>(c, p, B, pc, pd, lc, ld, ws, L, s, (fused_init && p == last) ? g : nullptr);
     if (st != TQS_OK) return st;
     pc = pd;
     lc = ld;
