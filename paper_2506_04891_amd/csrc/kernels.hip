@@ -1328,6 +1328,83 @@ __device__ __forceinline__ void run_stage(const Ctx<T, K> &c, const PassArgs<T> 
   __syncthreads();
 }
 
+// Embedding gradients of wires outside the embedding pass's tile, at the end of
+// its backward (lambda in LDS is the adjoint state at the embedding output).
+// The embedding output is a product state psi = (x)_k phi_k, so for an outside
+// wire w (its bit fixed to beta_w in this tile)
+//   <lambda| P_w |psi>|_tile = (P phi_w)(beta_w) * prod_{outside k != w} phi_k(beta_k)
+//                              * sum_{tile} conj(lambda) psi_tile,
+// with psi_tile the product over the tile's wires.  The last factor is a sum
+// over the workgroup's elements, so each thread's share goes to write_acc.
+template <typename T, int K>
+__device__ __forceinline__ void outside_embed_grads(const Ctx<T, K> &c, const PassArgs<T> &a, kptr<DevPass> P,
+                                                    const cplx<T> *Ll, uint32_t omask) {
+  constexpr int NT = Ctx<T, K>::NT;
+  const int n = c.n;
+  const int emat = uni(P->embed_mat);
+  kptr<cplx<T>> em = uni(P->embed_per_sample) ? a.mats_ps + (size_t)c.sample0 * a.mats_ps_stride + emat
+                                              : a.mats + emat;
+  // this thread's share of sum conj(lambda) psi_tile
+  cplx<T> cth = cmk<T>(1, 0);
+  for (int b = 0; b < K - RB; ++b) {
+    const int p = uni(P->tpos[b]);
+    cth = cmul(cth, kld(em + 4 * (n - 1 - p), ((c.tid >> b) & 1) ? 2 : 0));
+  }
+  cplx<T> f[RB][2];
+#pragma unroll
+  for (int b = 0; b < RB; ++b) {
+    kptr<cplx<T>> m = em + 4 * (n - 1 - uni(P->tpos[K - RB + b]));
+    f[b][0] = kld(m, 0);
+    f[b][1] = kld(m, 2);
+  }
+  double sx = 0.0, sy = 0.0;
+#pragma unroll
+  for (int i = 0; i < NREG; ++i) {
+    cplx<T> v = cth;
+#pragma unroll
+    for (int b = 0; b < RB; ++b) v = cmul(v, f[b][(i >> b) & 1]);
+    const cplx<T> l = Ll[swz<T>(c.tid + i * NT)];
+    sx += (double)l.x * v.x + (double)l.y * v.y;     // conj(l) v
+    sy += (double)l.x * v.y - (double)l.y * v.x;
+  }
+  const int tl = c.nv - K;
+  int acc = uni(P->outside_acc);
+  for (int q = 0; q < n; ++q) {
+    if (!((omask >> q) & 1)) continue;
+    const int beta = (c.base >> q) & 1;
+    kptr<cplx<T>> mw = em + 4 * (n - 1 - q);
+    const cplx<T> p0 = kld(mw, 0), p1 = kld(mw, 2);
+    // product of the other outside wires' components (double)
+    double rx = 1.0, ry = 0.0;
+    for (int r = 0; r < tl; ++r) {
+      const int k = uni(P->rest[r]);
+      if (k == q) continue;
+      const cplx<T> phi = kld(em + 4 * (n - 1 - k), ((c.base >> k) & 1) ? 2 : 0);
+      const double nx = rx * phi.x - ry * phi.y, ny = rx * phi.y + ry * phi.x;
+      rx = nx;
+      ry = ny;
+    }
+    // (P phi)(beta) for P = X, Y, Z
+    double cxr, cxi, cyr, cyi, czr, czi;
+    if (beta) {
+      cxr = p0.x; cxi = p0.y;           // X: phi_0
+      cyr = -p0.y; cyi = p0.x;          // Y: i phi_0
+      czr = -p1.x; czi = -p1.y;         // Z: -phi_1
+    } else {
+      cxr = p1.x; cxi = p1.y;           // X: phi_1
+      cyr = p1.y; cyi = -p1.x;          // Y: -i phi_1
+      czr = p0.x; czi = p0.y;           // Z: phi_0
+    }
+    const double cr[3] = {cxr, cyr, czr}, ci[3] = {cxi, cyi, czi};
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      const double dr = cr[k] * rx - ci[k] * ry, di = cr[k] * ry + ci[k] * rx;
+      write_acc(c, a, (T)(dr * sy + di * sx), acc + k);     // Im(D * S)
+    }
+    acc += 3;
+  }
+}
+
 // Occupancy targets of the single-precision tile passes: forward 3 waves per
 // SIMD (at most 168 registers), backward 2 (at most 256, shared by the
 // architectural and accumulation registers).  Double precision and the
@@ -1584,6 +1661,8 @@ __attribute__((amdgpu_waves_per_eu(PassOcc<T, BWD, DENSE>::waves))) k_pass(PassA
       const UStage S = load_stage(a.stages + gsb + si);
       run_stage<T, K, BWD, DENSE>(c, a, S, Lp, Ll, tab, true);
     }
+    const uint32_t omask = uniu(P->outside_mask);
+    if (omask && !c.multi) outside_embed_grads(c, a, P, Ll, omask);
     if (uni(P->skip_bwd_store)) return;
   }
 

@@ -137,7 +137,11 @@ struct DevPass {
   int32_t skip_bwd_store;    // backward of the first pass need not store
   int32_t diag_lds;          // complex elements of diag tables (and dense scratch) in LDS
   int32_t dense_off;         // LDS offset (elements, after the tiles) of the dense-op scratch, -1 if none
-  int32_t pad[2];
+  // embedding pass, backward: state bits outside the tile whose embed gradients are
+  // taken from the product-state environment (X, Y, Z sums per bit, ascending),
+  // starting at accumulator outside_acc
+  uint32_t outside_mask;
+  int32_t outside_acc;
 };
 
 // Parameter-preparation program (run on the device per call, FP64).

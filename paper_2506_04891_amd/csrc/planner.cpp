@@ -956,7 +956,27 @@ static std::string emit(Plan &P) {
     if (ok) P.passes[p].grad_wires.push_back(w);
     else leftovers.push_back(w);
   }
-  // gradient-only passes for the rest, prepended (they run last in the backward sweep)
+  // the rest: at the end of the embedding pass's backward, from the product-state
+  // environment (the embedding output is a product state, so the sums over pairs
+  // that straddle the tile factor into an in-tile overlap times outside factors)
+  int embed_pass = -1;
+  for (size_t p = 0; p < P.passes.size(); ++p)
+    if (P.passes[p].load_mode == LOAD_EMBED && !P.passes[p].bwd_only) {
+      embed_pass = (int)p;
+      break;
+    }
+  if (!leftovers.empty() && embed_pass >= 0 && P.nv > P.passes[embed_pass].K) {
+    for (int w : leftovers) {
+      const int b = n - 1 - w;
+      const auto &tl = P.passes[embed_pass].tile;
+      if (std::find(tl.begin(), tl.end(), b) != tl.end())
+        P.passes[embed_pass].grad_wires.push_back(w);
+      else
+        P.passes[embed_pass].outside_wires.push_back(w);
+    }
+    leftovers.clear();
+  }
+  // gradient-only passes for whatever is left, prepended (they run last in the backward sweep)
   if (!leftovers.empty()) {
     const int K = P.passes.empty() ? std::min(P.nv, KMAX) : P.passes[0].K;
     std::vector<PlanPass> extra;
@@ -1304,6 +1324,20 @@ static std::string emit(Plan &P) {
       }
     }
     d.n_grad_stages = (int)P.dstage.size() - d.grad_stage_begin;
+    // environment embed gradients (X, Y, Z sums per outside bit, ascending bit order)
+    d.outside_mask = 0;
+    d.outside_acc = -1;
+    if (!pp.outside_wires.empty()) {
+      std::vector<int> ob;
+      for (int w : pp.outside_wires) ob.push_back(n - 1 - w);
+      std::sort(ob.begin(), ob.end());
+      d.outside_acc = n_acc;
+      for (int b : ob) {
+        d.outside_mask |= 1u << b;
+        E.u1_contribs(P.embed[n - 1 - b], P.n_acc + n_acc);
+        n_acc += 3;
+      }
+    }
     d.n_acc = n_acc;
     // units per sample of this pass's partials
     int units;
@@ -1426,7 +1460,8 @@ std::string describe_plan(const Plan &P) {
       << ",\"u1_groups\":" << ngrp << ",\"u2\":" << nu2 << ",\"diag\":" << ndg << ",\"perm\":" << npm
       << ",\"dense\":" << ndense
       << ",\"grad_wires\":"
-      << pp.grad_wires.size() << ",\"n_acc\":" << d.n_acc << "}";
+      << pp.grad_wires.size() << ",\"outside_wires\":" << pp.outside_wires.size() << ",\"n_acc\":" << d.n_acc
+      << "}";
   }
   o << "]}";
   return o.str();

@@ -50,6 +50,7 @@ struct PlanPass {
   GF2 load_map, store_map;         // gather (src = load_map(k)), scatter (dst = store_map(k))
   bool bwd_only = false;           // gradient-only pass (embed gradients)
   std::vector<int> grad_wires;     // embed gradient wires handled at the end of this pass's backward
+  std::vector<int> outside_wires;  // embedding pass: embed gradients of wires outside its tile
 };
 
 struct Plan {
