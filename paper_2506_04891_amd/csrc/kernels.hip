@@ -645,6 +645,7 @@ struct PassArgs {
   kptr<DevTerm> terms;
   kptr<DevPerm> perms;
   kptr<DevGroup> groups;
+  kptr<DevSeq> seqs;
   kptr<cplx<T>> mats;
   kptr<cplx<T>> mats_ps;
   int mats_ps_stride;
@@ -860,6 +861,89 @@ __device__ __forceinline__ void u2g_run_k(const Ctx<T, K> &c, const PassArgs<T> 
     default: break;
   }
 }
+
+// The brick-layer stage program (OP_SEQ), straight-line.  Forward: pair gates
+// on (0,1),(2,3); 2x2 gates on bits 0-3; [pair gate on (1,2); [2x2 gates on
+// bits 1, 2]].  Backward runs the steps in reverse, each step's gradients taken
+// at its output before its inverse is applied to psi and lambda.
+template <typename T, int K, bool BWD, int R>
+__device__ __forceinline__ void seq_u1(const Ctx<T, K> &c, const PassArgs<T> &a, cplx<T> (&vp)[NREG],
+                                       cplx<T> (&vl)[NREG], kptr<DevSeq> q, int slot) {
+  const int mo = uni(q->mat[slot]);
+  kptr<cplx<T>> ms = a.mats + mo;
+  cplx<T> m[4];
+#pragma unroll
+  for (int k = 0; k < 4; ++k) m[k] = kld(ms, k);
+  if (BWD) {
+    const int ga = uni(q->acc[slot]);
+    if (ga >= 0) {
+      T sx = 0, sy = 0, sz = 0;
+      u1_grad<T, R>(vp, vl, sx, sy, sz);
+      write_acc(c, a, sx, ga + 0);
+      write_acc(c, a, sy, ga + 1);
+      write_acc(c, a, sz, ga + 2);
+    }
+  }
+  u1_apply<T, R, BWD>(vp, m);
+  if (BWD) u1_apply<T, R, true>(vl, m);
+}
+
+template <typename T, int K, bool BWD, int KIND, int R0, int R1>
+__device__ __forceinline__ void seq_u2(const Ctx<T, K> &c, const PassArgs<T> &a, cplx<T> (&vp)[NREG],
+                                       cplx<T> (&vl)[NREG], kptr<DevSeq> q, int slot) {
+  kptr<cplx<T>> mg = a.mats + uni(q->mat[slot]);
+  if (BWD && KIND == U2_MS) {
+    const int ga = uni(q->acc[slot]);
+    if (ga >= 0) write_acc(c, a, u2s_grad<T, R0, R1, true>(vp, vl), ga);
+  }
+  u2s_apply<T, R0, R1, BWD, KIND>(vp, mg);
+  if (BWD) u2s_apply<T, R0, R1, true, KIND>(vl, mg);
+}
+
+template <typename T, int K, bool BWD, int KIND, int LEN>
+__device__ __forceinline__ void seq_step(const Ctx<T, K> &c, const PassArgs<T> &a, cplx<T> (&vp)[NREG],
+                                         cplx<T> (&vl)[NREG], kptr<DevSeq> q) {
+  if (!BWD) {
+    seq_u2<T, K, false, KIND, 0, 1>(c, a, vp, vl, q, 0);
+    seq_u2<T, K, false, KIND, 2, 3>(c, a, vp, vl, q, 1);
+    seq_u1<T, K, false, 0>(c, a, vp, vl, q, 2);
+    seq_u1<T, K, false, 1>(c, a, vp, vl, q, 3);
+    seq_u1<T, K, false, 2>(c, a, vp, vl, q, 4);
+    seq_u1<T, K, false, 3>(c, a, vp, vl, q, 5);
+    if (LEN >= 3) seq_u2<T, K, false, KIND, 1, 2>(c, a, vp, vl, q, 6);
+    if (LEN >= 4) {
+      seq_u1<T, K, false, 1>(c, a, vp, vl, q, 7);
+      seq_u1<T, K, false, 2>(c, a, vp, vl, q, 8);
+    }
+  } else {
+    // gates acting on distinct bits commute: within a step the gradients can
+    // be taken in any order, all at the step's output
+    if (LEN >= 4) {
+      seq_u1<T, K, true, 2>(c, a, vp, vl, q, 8);
+      seq_u1<T, K, true, 1>(c, a, vp, vl, q, 7);
+    }
+    if (LEN >= 3) seq_u2<T, K, true, KIND, 1, 2>(c, a, vp, vl, q, 6);
+    seq_u1<T, K, true, 3>(c, a, vp, vl, q, 5);
+    seq_u1<T, K, true, 2>(c, a, vp, vl, q, 4);
+    seq_u1<T, K, true, 1>(c, a, vp, vl, q, 3);
+    seq_u1<T, K, true, 0>(c, a, vp, vl, q, 2);
+    seq_u2<T, K, true, KIND, 2, 3>(c, a, vp, vl, q, 1);
+    seq_u2<T, K, true, KIND, 0, 1>(c, a, vp, vl, q, 0);
+  }
+}
+
+template <typename T, int K, bool BWD>
+__device__ __forceinline__ void seq_run(const Ctx<T, K> &c, const PassArgs<T> &a, cplx<T> (&vp)[NREG],
+                                        cplx<T> (&vl)[NREG], kptr<DevSeq> q, int len, int sub) {
+  switch (sub * 8 + len) {
+#define X(kind, l) \
+  case kind * 8 + l: { TQS_CASE_MARK(S##kind##l); seq_step<T, K, BWD, kind, l>(c, a, vp, vl, q); TQS_CASE_MARK(eS##kind##l); break; }
+    X(U2_MS, 2) X(U2_MS, 3) X(U2_MS, 4) X(U2_ECR, 2) X(U2_ECR, 3) X(U2_ECR, 4)
+#undef X
+    default: break;
+  }
+}
+
 
 
 
@@ -1245,6 +1329,8 @@ __device__ __forceinline__ void run_stage(const Ctx<T, K> &c, const PassArgs<T> 
         for (int q = 0; q < 4; ++q) m[r][q] = kld(ms, q);
       }
       u1g_run<T, K, BWD>(c, a, vp, vl, m, ga, op.r0);
+    } else if (op.kind == OP_SEQ) {
+      seq_run<T, K, BWD>(c, a, vp, vl, a.seqs + op.aux, op.r0, op.sub);
     } else if (op.kind == OP_U2G) {
       kptr<DevGroup> gp = a.groups + op.aux;
       kptr<cplx<T>> m0 = a.mats + uni(gp->mat[0]), m1 = a.mats + uni(gp->mat[1]);

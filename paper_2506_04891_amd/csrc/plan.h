@@ -38,6 +38,10 @@ enum OpKind : int32_t {
                  // aux = DevGroup index (the gates act on distinct bits, so they commute)
   OP_U2G = 9,    // two structured 4x4 gates of one kind (sub) on disjoint register-bit
                  // pairs: r0 = a<<6 | b<<4 | c<<2 | d for pairs (a,b), (c,d); aux = DevGroup
+  OP_SEQ = 10,   // the brick-layer stage program, one op: pair gates of kind `sub` on
+                 // register pairs (0,1),(2,3); 2x2 gates on bits 0-3; then (r0 >= 3) a pair
+                 // gate on (1,2); then (r0 == 4) 2x2 gates on bits 1, 2.  r0 = program
+                 // length (2..4), aux = DevSeq index
 };
 
 enum OpFlag : int32_t {
@@ -101,6 +105,15 @@ struct DevTerm {
 struct DevGroup {
   int32_t mat[RB];
   int32_t acc[RB];
+};
+
+// Members of an OP_SEQ op: slots 0-1 the pair gates on (0,1), (2,3); 2-5 the
+// 2x2 gates on bits 0-3; 6 the pair gate on (1,2); 7-8 the 2x2 gates on bits
+// 1, 2.  Matrix offset and first gradient accumulator (-1: none).
+constexpr int SEQ_SLOTS = 9;
+struct DevSeq {
+  int32_t mat[SEQ_SLOTS];
+  int32_t acc[SEQ_SLOTS];
 };
 
 // In-tile permutation: dst tile index t takes src = xor of cols[i] over set bits i of t, ^ cxor.

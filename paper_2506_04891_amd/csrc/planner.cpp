@@ -719,6 +719,71 @@ static void group_u2(Plan &P, int begin) {
   P.dop.insert(P.dop.end(), out.begin(), out.end());
 }
 
+// The stage program of brick-layer circuits -- pair gates on (0,1),(2,3), 2x2
+// gates on all four register bits, a pair gate on (1,2), 2x2 gates on bits 1
+// and 2 (or a prefix of at least the first two steps) -- becomes one OP_SEQ op:
+// straight-line code for the whole run, with no op-loop merge between steps.
+static void group_seq(Plan &P, int begin) {
+  std::vector<DevOp> out;
+  size_t i = begin;
+  const size_t end = P.dop.size();
+  while (i < end) {
+    const DevOp &a = P.dop[i];
+    const bool head = a.kind == OP_U2G && a.r0 == (0 << 6 | 1 << 4 | 2 << 2 | 3) &&
+                      i + 1 < end && P.dop[i + 1].kind == OP_U1G && P.dop[i + 1].r0 == 15;
+    if (!head) {
+      out.push_back(P.dop[i++]);
+      continue;
+    }
+    int len = 2;
+    if (i + 2 < end) {
+      const DevOp &u = P.dop[i + 2];
+      if (u.kind == OP_U2 && u.r0 == 1 && u.r1 == 2 && u.sub == a.sub && !(u.flags & F_PERSAMPLE)) {
+        len = 3;
+        if (i + 3 < end && P.dop[i + 3].kind == OP_U1G && P.dop[i + 3].r0 == 6) len = 4;
+      }
+    }
+    DevSeq q;
+    for (int k = 0; k < SEQ_SLOTS; ++k) q.mat[k] = q.acc[k] = -1;
+    const DevGroup &g2 = P.dgroup[a.aux];
+    q.mat[0] = g2.mat[0];
+    q.mat[1] = g2.mat[1];
+    q.acc[0] = g2.acc[0];
+    q.acc[1] = g2.acc[1];
+    const DevGroup &g1 = P.dgroup[P.dop[i + 1].aux];
+    for (int r = 0; r < RB; ++r) {
+      q.mat[2 + r] = g1.mat[r];
+      q.acc[2 + r] = g1.acc[r];
+    }
+    if (len >= 3) {
+      const DevOp &u = P.dop[i + 2];
+      q.mat[6] = u.mat;
+      q.acc[6] = (u.flags & F_GRAD) ? u.acc : -1;
+    }
+    if (len == 4) {
+      const DevGroup &g3 = P.dgroup[P.dop[i + 3].aux];
+      q.mat[7] = g3.mat[1];
+      q.acc[7] = g3.acc[1];
+      q.mat[8] = g3.mat[2];
+      q.acc[8] = g3.acc[2];
+    }
+    DevOp o;
+    std::memset(&o, 0, sizeof o);
+    o.kind = OP_SEQ;
+    o.sub = a.sub;
+    o.r0 = len;
+    o.acc = -1;
+    for (int k = 0; k < SEQ_SLOTS; ++k)
+      if (q.acc[k] >= 0) o.flags |= F_GRAD;
+    o.aux = (int)P.dseq.size();
+    P.dseq.push_back(q);
+    out.push_back(o);
+    i += len;
+  }
+  P.dop.resize(begin);
+  P.dop.insert(P.dop.end(), out.begin(), out.end());
+}
+
 static std::string schedule(Plan &P, int K) {
   const int n = P.n;
   P.passes.clear();
@@ -880,6 +945,7 @@ static std::string emit(Plan &P) {
   P.dterm.clear();
   P.dperm.clear();
   P.dgroup.clear();
+  P.dseq.clear();
   P.prep.clear();
   P.contribs.clear();
   P.n_mats = P.n_mats_ps = P.n_dbl = P.n_dbl_ps = 0;
@@ -1280,6 +1346,7 @@ static std::string emit(Plan &P) {
       if (!emit_error.empty()) return emit_error;
       group_u1(P, st.op_begin);
       group_u2(P, st.op_begin);
+      group_seq(P, st.op_begin);
       st.op_end = (int)P.dop.size();
       P.dstage.push_back(st);
       prev_regs = S;
@@ -1445,6 +1512,12 @@ std::string describe_plan(const Plan &P) {
         nu1 += k == OP_U1;
         if (k == OP_U1G) {
           nu1 += __builtin_popcount((unsigned)P.dop[oi].r0);
+          ++ngrp;
+        }
+        if (k == OP_SEQ) {
+          const int len = P.dop[oi].r0;
+          nu1 += 4 + (len == 4 ? 2 : 0);
+          nu2 += 2 + (len >= 3 ? 1 : 0);
           ++ngrp;
         }
         nu2 += (k == OP_U2) + 2 * (k == OP_U2G);

@@ -73,6 +73,7 @@ struct Plan {
   std::vector<DevTerm> dterm;
   std::vector<DevPerm> dperm;
   std::vector<DevGroup> dgroup;
+  std::vector<DevSeq> dseq;
   std::vector<PrepItem> prep;
   std::vector<Contrib> contribs;
   std::vector<int> cptr;                 // CSR over params: weights then features

@@ -66,6 +66,7 @@ struct tqs_circuit {
   DevTerm *d_term = nullptr;
   DevPerm *d_perm = nullptr;
   DevGroup *d_group = nullptr;
+  DevSeq *d_seq = nullptr;
   PrepItem *d_prep = nullptr;
   Factor *d_fac = nullptr;
   Contrib *d_contrib = nullptr;
@@ -138,6 +139,7 @@ tqs_status upload(tqs_circuit *c) {
       {P.dterm.data(), bytes_of(P.dterm), (void **)&c->d_term},
       {P.dperm.data(), bytes_of(P.dperm), (void **)&c->d_perm},
       {P.dgroup.data(), bytes_of(P.dgroup), (void **)&c->d_group},
+      {P.dseq.data(), bytes_of(P.dseq), (void **)&c->d_seq},
       {P.prep.data(), bytes_of(P.prep), (void **)&c->d_prep},
       {P.factors.data(), bytes_of(P.factors), (void **)&c->d_fac},
       {P.contribs.data(), bytes_of(P.contribs), (void **)&c->d_contrib},
@@ -302,6 +304,7 @@ tqs_status launch_pass(tqs_circuit *c, int pi, int B, const cplx<T> *src0, cplx<
   a.terms = kc(c->d_term);
   a.perms = kc(c->d_perm);
   a.groups = kc(c->d_group);
+  a.seqs = kc(c->d_seq);
   a.mats = kc(reinterpret_cast<const cplx<T> *>(ws + L.mats));
   a.mats_ps = kc(reinterpret_cast<const cplx<T> *>(ws + L.mats_ps));
   a.mats_ps_stride = P.n_mats_ps;
@@ -333,6 +336,17 @@ tqs_status launch_pass(tqs_circuit *c, int pi, int B, const cplx<T> *src0, cplx<
       for (int oi = P.dstage[st].op_begin; oi < P.dstage[st].op_end; ++oi) {
         if (P.dop[oi].kind == OP_DENSE) {
           f += (BWD ? 2.0 : 1.0) * dense_flops(P.nv);
+        } else if (P.dop[oi].kind == OP_SEQ) {
+          // two pair gates, four 2x2, [one pair gate, [two 2x2]]
+          const DevSeq &q = P.dseq[P.dop[oi].aux];
+          for (int k = 0; k < SEQ_SLOTS; ++k) {
+            if (q.mat[k] < 0) continue;
+            const bool pair = k < 2 || k == 6;
+            if (pair)
+              f += BWD ? 12.0 + (q.acc[k] >= 0 ? 8.0 : 0.0) : 6.0;
+            else
+              f += BWD ? 28.0 + (q.acc[k] >= 0 ? 18.0 : 0.0) : 14.0;
+          }
         } else if (P.dop[oi].kind == OP_U2G) {
           // two structured pair gates (6 flop/amp each); MS gradients 8 each
           const DevGroup &g = P.dgroup[P.dop[oi].aux];
