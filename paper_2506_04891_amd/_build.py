@@ -33,22 +33,40 @@ def _stale(obj, sources):
     return any(os.path.getmtime(src) > t for src in sources)
 
 
+PASS_UNITS = ("pass_f32_fwd", "pass_f32_bwd", "pass_f64_fwd", "pass_f64_bwd")
+
+
 def build(verbose=False, if_changed=False):
-    """Compile the planner and the HIP translation unit, link libtqsim.so.
-    if_changed: skip the HIP compile when its object is newer than every file
-    it includes (for quick rebuilds after host-only changes)."""
+    """Compile the planner and the HIP translation units (the host API and one
+    unit per element type and direction of the tile-pass kernels, in
+    parallel), link libtqsim.so.
+    if_changed: skip a HIP compile whose object is newer than every file it
+    includes (for quick rebuilds after host-only changes)."""
     os.makedirs(BUILD, exist_ok=True)
     planner_o = os.path.join(BUILD, "planner.o")
-    tqsim_o = os.path.join(BUILD, "tqsim.o")
     inc = ["-I", CSRC, "-I", INCLUDE]
+    common = [os.path.join(CSRC, f) for f in ("kernels.hip", "plan.h", "planner.h", "pass_launch.h",
+                                               "pass_tu.inc")]
+    common.append(os.path.join(INCLUDE, "tqsim.h"))
+    units = ["tqsim", *PASS_UNITS]
+    procs, objs = [], []
+    for u in units:
+        src = os.path.join(CSRC, u + ".hip")
+        obj = os.path.join(BUILD, u + ".o")
+        objs.append(obj)
+        if if_changed and not _stale(obj, [src, *common]):
+            continue
+        cmd = ["hipcc", *HIP_FLAGS, *inc, "-c", src, "-o", obj]
+        procs.append((cmd, subprocess.Popen(cmd, stdout=subprocess.PIPE, stderr=subprocess.STDOUT, text=True)))
     _run(["g++", "-O2", "-fPIC", "-std=c++17", "-Wall", *inc, "-c",
           os.path.join(CSRC, "planner.cpp"), "-o", planner_o])
-    hip_srcs = [os.path.join(CSRC, f) for f in ("tqsim.hip", "kernels.hip", "plan.h", "planner.h")]
-    hip_srcs.append(os.path.join(INCLUDE, "tqsim.h"))
-    if not if_changed or _stale(tqsim_o, hip_srcs):
-        _run(["hipcc", *HIP_FLAGS, *inc, "-c", os.path.join(CSRC, "tqsim.hip"), "-o", tqsim_o])
+    for cmd, pr in procs:
+        out, _ = pr.communicate()
+        if pr.returncode != 0:
+            lines = [ln for ln in out.splitlines() if "packed-fp32-ops" not in ln]
+            raise RuntimeError("build failed: " + " ".join(cmd) + "\n" + "\n".join(lines[-80:]))
     tmp = LIB + ".tmp"
-    _run(["hipcc", "-shared", "-fPIC", "--offload-arch=gfx950", tqsim_o, planner_o, "-o", tmp])
+    _run(["hipcc", "-shared", "-fPIC", "--offload-arch=gfx950", *objs, planner_o, "-o", tmp])
     os.replace(tmp, LIB)
     if verbose:
         print("built", LIB)

@@ -1946,6 +1946,7 @@ constexpr int NTR = 256;   // threads per block of the grouped reduction kernels
 
 // expz[b, i] and norm[b] from the partials; wire i <-> state bit p = n-1-i.
 // A group of 2^gl lanes per output (b, i); i == n gives the norm.
+#ifndef TQS_PASS_TU   // defined once, in the translation unit of the host API
 __global__ void __launch_bounds__(NTR) k_expval_final(const double *partials, double *expz, double *norm, int n,
                                                       int batch, int gl) {
   const long long o = ((long long)blockIdx.x * NTR + threadIdx.x) >> gl;
@@ -1975,6 +1976,7 @@ __global__ void __launch_bounds__(NTR) k_expval_final(const double *partials, do
     }
   }
 }
+#endif
 
 // lambda = psi * h with h(j) = sum_i g_i (1 - 2 b_i(j)), per sample
 template <typename T, bool COAL>
@@ -2043,6 +2045,7 @@ __global__ void __launch_bounds__(NTR) k_acc_reduce(const T *partials, const lon
 
 // weight gradients: sum over samples of the accumulator combinations; one
 // group of 2^gl lanes per weight, lanes striding over the batch
+#ifndef TQS_PASS_TU   // defined once, in the translation unit of the host API
 __global__ void __launch_bounds__(NTR) k_grad_weights(const int *cptr, const Contrib *contribs, const double *A,
                                                       const double *dbl, const double *dbl_ps, int dbl_ps_stride,
                                                       int n_w, int batch, double *gw, int gl) {
@@ -2062,8 +2065,10 @@ __global__ void __launch_bounds__(NTR) k_grad_weights(const int *cptr, const Con
   s = seg_sum_dpp(s, gl);
   if (valid && g == (1 << gl) - 1) gw[o] = s;
 }
+#endif
 
 // feature gradients: one thread per (sample, feature)
+#ifndef TQS_PASS_TU   // defined once, in the translation unit of the host API
 __global__ void __launch_bounds__(NTR) k_grad_features(const int *cptr, const Contrib *contribs, const double *A,
                                                        const double *dbl, const double *dbl_ps, int dbl_ps_stride,
                                                        int n_w, int n_x, int batch, double *gx) {
@@ -2079,5 +2084,6 @@ __global__ void __launch_bounds__(NTR) k_grad_features(const int *cptr, const Co
   }
   gx[(long long)b * n_x + f] = s;
 }
+#endif
 
 }  // namespace tqs

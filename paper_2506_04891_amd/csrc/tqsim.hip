@@ -8,6 +8,7 @@
 #include <vector>
 
 #include "kernels.hip"
+#include "pass_launch.h"
 #include "planner.h"
 #include "tqsim.h"
 
@@ -94,29 +95,11 @@ size_t bytes_of(const std::vector<V> &v) {
 
 std::once_flag g_attr_once;
 
-template <typename T, int K, bool BWD, bool DENSE = false>
-void set_lds_attr() {
-  (void)hipFuncSetAttribute(reinterpret_cast<const void *>(&k_pass<T, K, BWD, DENSE>),
-                            hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
-}
-
 void set_all_attrs() {
-  set_lds_attr<float, 10, false>();
-  set_lds_attr<float, 11, false>();
-  set_lds_attr<float, 12, false>();
-  set_lds_attr<float, 10, true>();
-  set_lds_attr<float, 11, true>();
-  set_lds_attr<float, 12, true>();
-  set_lds_attr<double, 10, false>();
-  set_lds_attr<double, 11, false>();
-  set_lds_attr<double, 12, false>();
-  set_lds_attr<double, 10, true>();
-  set_lds_attr<double, 11, true>();
-  set_lds_attr<double, 12, true>();
-  set_lds_attr<float, 10, false, true>();
-  set_lds_attr<float, 10, true, true>();
-  set_lds_attr<double, 10, false, true>();
-  set_lds_attr<double, 10, true, true>();
+  pass_attrs_f32_fwd();
+  pass_attrs_f32_bwd();
+  pass_attrs_f64_fwd();
+  pass_attrs_f64_bwd();
 }
 
 tqs_status upload(tqs_circuit *c) {
@@ -285,10 +268,6 @@ double op_flops_bwd(const DevOp &o) {
   return f;
 }
 
-template <typename T, int K, bool BWD, bool DENSE = false>
-void launch_pass_k(const PassArgs<T> &a, int grid, size_t lds, hipStream_t s) {
-  hipLaunchKernelGGL((k_pass<T, K, BWD, DENSE>), dim3(grid), dim3(1 << (K - RB)), lds, s, a);
-}
 
 template <typename T, bool BWD>
 tqs_status launch_pass(tqs_circuit *c, int pi, int B, const cplx<T> *src0, cplx<T> *dst0,
@@ -369,19 +348,8 @@ tqs_status launch_pass(tqs_circuit *c, int pi, int B, const cplx<T> *src0, cplx<
                          (sizeof(T) == 8 ? "_c128" : "_c64"), bytes, flops);
   // passes holding full-layer matrix ops use their own instantiation, so that
   // the matrix-core code does not raise the register use of the others
-  if (d.dense_off >= 0) {
-    if (d.K != 10) return fail(TQS_EUNSUPPORTED, "dense layers need a 10-bit tile");
-    launch_pass_k<T, 10, BWD, true>(a, grid, lds, s);
-    ps.end();
-    HIP_TRY(hipGetLastError());
-    return TQS_OK;
-  }
-  switch (d.K) {
-    case 10: launch_pass_k<T, 10, BWD>(a, grid, lds, s); break;
-    case 11: launch_pass_k<T, 11, BWD>(a, grid, lds, s); break;
-    case 12: launch_pass_k<T, 12, BWD>(a, grid, lds, s); break;
-    default: return fail(TQS_EUNSUPPORTED, "tile size not built");
-  }
+  if (!PassLaunch<T, BWD>::run(a, d.K, d.dense_off >= 0, grid, lds, s))
+    return fail(TQS_EUNSUPPORTED, d.dense_off >= 0 ? "dense layers need a 10-bit tile" : "tile size not built");
   ps.end();
   HIP_TRY(hipGetLastError());
   return TQS_OK;

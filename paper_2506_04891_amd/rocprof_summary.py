@@ -30,7 +30,7 @@ def sources_sha256():
     h = hashlib.sha256()
     root = os.path.join(HERE, "csrc")
     for name in sorted(os.listdir(root)):
-        if name.endswith((".hip", ".h", ".cpp")):
+        if name.endswith((".hip", ".h", ".cpp", ".inc")):
             with open(os.path.join(root, name), "rb") as f:
                 h.update(name.encode() + b"\0" + f.read())
     hdr = os.path.join(os.path.dirname(HERE), "include", "tqsim.h")
