@@ -50,6 +50,8 @@ def parse():
     # instead of the benchmark: time every configuration under each dispatch
     # mode and tile size, one JSON line per case
     p.add_argument("--dispatch-sweep", action="store_true")
+    p.add_argument("--vq-qdi-sweep", action="store_true",
+                   help="forward/backward/total time vs qubits for the VQ and QDI encodings")
     return p.parse_args()
 
 
@@ -289,6 +291,51 @@ def dispatch_sweep(iters=10):
                                   "evals_per_s": round(B / ms * 1e3, 1)}), flush=True)
 
 
+def vq_qdi_sweep(iters=20):
+    """Fig. 8's measurement on the Rz-Ry-CNOT circuit of Fig. 6 (8 blocks):
+    forward (+ <Z_i>), backward (adjoint) and total time per call against the
+    number of qubits, at batch 1 and 64, for VQ and QDI encodings (c64)."""
+    import torch
+    import workloads as W
+    from paper_2506_04891_amd import tqsim as T
+    dev = torch.device("cuda")
+    for enc in ("vq", "qdi"):
+        for B in (1, 64):
+            for n in (4, 6, 8, 10, 12, 14, 16, 18, 20, 22):
+                if B * (8 << n) > (4 << 30):
+                    continue
+                layers = W.circuit_rz_ry_cnot(n, 8, enc)
+                c = T.Circuit(n, layers, "c64")
+                w, x = W.draw_params(n, layers, B, "normal", 0)
+                wt, xt = torch.tensor(w, device=dev), torch.tensor(x, device=dev)
+                g = torch.ones((B, n), dtype=torch.float64, device=dev)
+                st = torch.empty((B, 2 ** n), dtype=c.complex_dtype, device=dev)
+                ws = c.workspace(B, True, dev)
+
+                def fwd():
+                    c.forward(wt, xt, state=st, ws=ws)
+                    c.expval_z(st, ws=ws)
+
+                def step():
+                    fwd()
+                    c.adjoint_grad(wt, xt, st, g, ws=ws)
+
+                row = {"encoding": enc, "batch": B, "n": n, "passes": len(c.plan()["passes"])}
+                for name, fn in (("fwd", fwd), ("total", step)):
+                    for _ in range(3):
+                        fn()
+                    torch.cuda.synchronize()
+                    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                    e0.record()
+                    for _ in range(iters):
+                        fn()
+                    e1.record()
+                    torch.cuda.synchronize()
+                    row[name + "_us"] = round(e0.elapsed_time(e1) / iters * 1e3, 1)
+                row["bwd_us"] = round(row["total_us"] - row["fwd_us"], 1)
+                print(json.dumps(row), flush=True)
+
+
 def _oracle_samples(samples, seed_offset=0, keep=None):
     """Seconds the oracle (numpy complex128, one BLAS thread) takes for forward
     <Z_i> + adjoint gradients of `samples` rows of each 16-qubit circuit.
@@ -375,7 +422,7 @@ def main():
     # the CPU baselines run first: the pooled one forks, which must happen
     # before anything initialises the GPU in this process
     oracle_rows = {}
-    sweep = a.dense_sweep or a.dispatch_sweep
+    sweep = a.dense_sweep or a.dispatch_sweep or a.vq_qdi_sweep
     cpu = None if (a.no_cpu_baseline or sweep) else cpu_baseline(keep=oracle_rows)
     cpu_pool = None if (a.no_cpu_baseline or sweep) else cpu_baseline_pool()
     import torch
@@ -389,6 +436,9 @@ def main():
         return
     if a.dispatch_sweep:
         dispatch_sweep()
+        return
+    if a.vq_qdi_sweep:
+        vq_qdi_sweep()
         return
 
     jobs = [Job("c4a_16q_b128_ionq", a.mode), Job("c4b_16q_b128_ibm", a.mode)]

@@ -1318,13 +1318,14 @@ __device__ __forceinline__ void run_stage(const Ctx<T, K> &c, const PassArgs<T> 
     } else if (op.kind == OP_U1G) {
       // the members commute, so every gradient is taken at the group's output
       kptr<DevGroup> gp = a.groups + op.aux;
+      kptr<cplx<T>> mbase = (op.flags & F_PERSAMPLE) ? a.mats_ps + (size_t)s_thr * a.mats_ps_stride : a.mats;
       cplx<T> m[RB][4];
       int ga[RB];
 #pragma unroll
       for (int r = 0; r < RB; ++r) {
         const int mo = uni(gp->mat[r]);
         ga[r] = (op.flags & F_GRAD) ? uni(gp->acc[r]) : -1;
-        kptr<cplx<T>> ms = a.mats + (mo < 0 ? 0 : mo);
+        kptr<cplx<T>> ms = mbase + (mo < 0 ? 0 : mo);
 #pragma unroll
         for (int q = 0; q < 4; ++q) m[r][q] = kld(ms, q);
       }

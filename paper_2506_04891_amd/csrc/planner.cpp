@@ -631,9 +631,8 @@ struct Sched {
 // register bits of one stage become one OP_U1G op: they commute, so the kernel
 // applies them back to back and takes their gradients at the group's output.
 static void group_u1(Plan &P, int begin) {
-  auto eligible = [](const DevOp &o) {
-    return o.kind == OP_U1 && !(o.flags & (F_PERSAMPLE | F_REAL | F_DIAGONAL));
-  };
+  // members share one table: all shared matrices or all per-sample ones
+  auto eligible = [](const DevOp &o) { return o.kind == OP_U1 && !(o.flags & (F_REAL | F_DIAGONAL)); };
   std::vector<DevOp> out;
   size_t i = begin;
   while (i < P.dop.size()) {
@@ -641,9 +640,12 @@ static void group_u1(Plan &P, int begin) {
       out.push_back(P.dop[i++]);
       continue;
     }
+    const int ps = P.dop[i].flags & F_PERSAMPLE;
     size_t j = i;
     int mask = 0;
-    while (j < P.dop.size() && eligible(P.dop[j]) && !(mask & (1 << P.dop[j].r0))) mask |= 1 << P.dop[j++].r0;
+    while (j < P.dop.size() && eligible(P.dop[j]) && (P.dop[j].flags & F_PERSAMPLE) == ps &&
+           !(mask & (1 << P.dop[j].r0)))
+      mask |= 1 << P.dop[j++].r0;
     if (j - i < 2) {
       out.push_back(P.dop[i++]);
       continue;
@@ -661,6 +663,7 @@ static void group_u1(Plan &P, int begin) {
       }
     }
     o.kind = OP_U1G;
+    o.flags |= ps;
     o.r0 = mask;
     o.acc = -1;
     o.aux = (int)P.dgroup.size();
@@ -729,8 +732,10 @@ static void group_seq(Plan &P, int begin) {
   const size_t end = P.dop.size();
   while (i < end) {
     const DevOp &a = P.dop[i];
+    // the stage program reads shared matrices only
     const bool head = a.kind == OP_U2G && a.r0 == (0 << 6 | 1 << 4 | 2 << 2 | 3) &&
-                      i + 1 < end && P.dop[i + 1].kind == OP_U1G && P.dop[i + 1].r0 == 15;
+                      i + 1 < end && P.dop[i + 1].kind == OP_U1G && P.dop[i + 1].r0 == 15 &&
+                      !(P.dop[i + 1].flags & F_PERSAMPLE);
     if (!head) {
       out.push_back(P.dop[i++]);
       continue;
@@ -740,7 +745,9 @@ static void group_seq(Plan &P, int begin) {
       const DevOp &u = P.dop[i + 2];
       if (u.kind == OP_U2 && u.r0 == 1 && u.r1 == 2 && u.sub == a.sub && !(u.flags & F_PERSAMPLE)) {
         len = 3;
-        if (i + 3 < end && P.dop[i + 3].kind == OP_U1G && P.dop[i + 3].r0 == 6) len = 4;
+        if (i + 3 < end && P.dop[i + 3].kind == OP_U1G && P.dop[i + 3].r0 == 6 &&
+            !(P.dop[i + 3].flags & F_PERSAMPLE))
+          len = 4;
       }
     }
     DevSeq q;

@@ -154,8 +154,9 @@ class Circuit:
 
     def __del__(self):
         h = getattr(self, "_h", None)
-        if h is not None:
-            with _released_lock:
+        lock = _released_lock
+        if h is not None and lock is not None:   # None at interpreter shutdown
+            with lock:
                 _released.append(h)
             self._h = None
 

@@ -217,8 +217,8 @@ def test_deterministic_repeat():
 
 # ---------------------------------------------------------------- full size --
 
-def _sampled_full(name, samples):
-    n, B, dt, layers, w, x = W.config(name)
+def _sampled_full(name, samples, spec=None):
+    n, B, dt, layers, w, x = spec if spec is not None else W.config(name)
     g = np.zeros((B, n))
     g[samples] = W.upstream(len(samples), n, "normal", 9)
     note(f"case full {name} samples={samples}")
@@ -250,3 +250,32 @@ def test_full_c4b_sampled():
 
 def test_full_c3_sampled():
     _sampled_full("c3_20q_b32", [31])
+
+
+# ------------------------------------------- Fig. 6 circuit, VQ and QDI --
+
+@pytest.mark.parametrize("encoding", ["vq", "qdi"])
+@pytest.mark.parametrize("n,dtype,mode,B", [
+    (4, "c128", "auto", 5), (4, "c128", "dense", 5), (6, "c64", "dense", 3),
+    (9, "c64", "per_layer", 3), (9, "c64", "fused", 3), (12, "c64", "fused", 3),
+    (13, "c128", "fused", 2), (14, "c64", "per_layer", 2), (16, "c64", "fused", 2),
+])
+def test_rz_ry_cnot_vq_qdi(encoding, n, dtype, mode, B):
+    """The Rz-Ry-CNOT circuit of Sec. 3 with features in the first RZ layer
+    (VQ) or in all eight (QDI, one shared feature column per wire)."""
+    layers = W.circuit_rz_ry_cnot(n, 8, encoding)
+    w, x, g = _params(n, layers, B, seed=30 + n)
+    note(f"case fig6 {encoding} n={n} {dtype} mode={mode} B={B}")
+    got = gpu_run(_circuit(n, layers, dtype, mode), w, x, g)
+    ref = oracle_run(n, layers, w, x, g)
+    compare(got, ref, dtype, label=f"fig6 {encoding} n={n} {mode}")
+
+
+@pytest.mark.parametrize("encoding", ["vq", "qdi"])
+def test_rz_ry_cnot_16q_b64_sampled(encoding):
+    """Fig. 8's batch-64 shape at 16 qubits, whole batch on the GPU, sampled
+    rows against the oracle."""
+    n, B = 16, 64
+    layers = W.circuit_rz_ry_cnot(n, 8, encoding)
+    w, x = W.draw_params(n, layers, B, "normal", 6)
+    _sampled_full(f"fig6 {encoding}", [0, 63], spec=(n, B, "c64", layers, w, x))

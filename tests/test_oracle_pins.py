@@ -331,3 +331,55 @@ def test_rz_before_readout_has_zero_gradient():
     x = RNG.uniform(-3, 3, (2, 3))
     _, gw, _ = sim.grad_adjoint(n, layers, w, x, W.upstream(2, n, "normal", 1))
     np.testing.assert_allclose(gw, 0.0, atol=1e-14)
+
+
+def _untied_qdi(n, blocks):
+    """The QDI circuit with a separate feature column block per RZ layer."""
+    out, k = [], 0
+    for ly in W.circuit_rz_ry_cnot(n, blocks, "qdi"):
+        if ly.source == "INPUT":
+            ly = ly._replace(offset=k * n)
+            k += 1
+        out.append(ly)
+    return out
+
+
+@pytest.mark.parametrize("n", [3, 4])
+def test_qdi_reuploaded_feature_gradient(n):
+    """Sec. 3, QDI encoding: the features enter every RZ layer, so dL/dx_q is
+    the sum over blocks of the gradients of a circuit whose RZ layers have
+    their own copies of x (the chain rule for a shared input), and it agrees
+    with central differences of the tied circuit."""
+    blocks = 3
+    layers = W.circuit_rz_ry_cnot(n, blocks, "qdi")
+    assert W.circuit_counts(n, layers)[1] == n
+    w, x = W.draw_params(n, layers, 2, "normal", 21)
+    g = W.upstream(2, n, "normal", 4)
+    e, gw, gx = sim.grad_adjoint(n, layers, w, x, g)
+    untied = _untied_qdi(n, blocks)
+    xu = np.tile(x, (1, blocks))
+    eu, gwu, gxu = sim.grad_adjoint(n, untied, w, xu, g)
+    np.testing.assert_allclose(e, eu, atol=1e-14)
+    np.testing.assert_allclose(gw, gwu, atol=1e-13)
+    np.testing.assert_allclose(gx, gxu.reshape(2, blocks, n).sum(axis=1), atol=1e-13)
+    fw, fx = sim.grad_fd(n, layers, w, x, g)
+    np.testing.assert_allclose(gw, fw, atol=1e-7)
+    np.testing.assert_allclose(gx, fx, atol=1e-7)
+    # the per-block contributions differ, so a gradient that kept only one
+    # block's share would fail the sum above
+    per_block = gxu.reshape(2, blocks, n)
+    assert np.max(np.abs(per_block[:, 0] - gx)) > 1e-3
+
+
+def test_vq_encodes_first_rz_only():
+    """Sec. 3, VQ encoding: one feature layer (the first RZ), the other RZ
+    layers trained; with all weights zero the state after the trained RY and
+    the CNOT ring is |0...0>, on which RZ(x) is a pure phase."""
+    n, blocks = 4, 3
+    layers = W.circuit_rz_ry_cnot(n, blocks, "vq")
+    nw, nf = W.circuit_counts(n, layers)
+    assert nf == n and nw == n * (1 + 2 * blocks - 1)
+    assert [ly.source for ly in layers if ly.gate == "RZ"] == ["INPUT"] + ["WEIGHT"] * (blocks - 1)
+    x = np.random.default_rng(5).uniform(-np.pi, np.pi, (2, n))
+    e = sim.forward_expval(n, layers, np.zeros(nw), x)
+    np.testing.assert_allclose(e, 1.0, atol=1e-14)

@@ -138,6 +138,27 @@ def circuit_rot_ring(n, blocks, embed="RY", rots=("RY", "RZ"), zz=False):
     return b.layers
 
 
+def circuit_rz_ry_cnot(n, blocks=8, encoding="qdi"):
+    """The Rz-Ry-CNOT benchmark circuit of Sec. 3 (Fig. 6): a trained RY layer
+    and a CNOT ring, then ``blocks`` x [RZ, RY, CNOT ring].
+
+    encoding "vq" (vanilla quantum): the features enter the first RZ layer
+    only; later RZ layers are trained.  encoding "qdi" (quantum depth
+    infused): every RZ layer takes the same n features (feature q on wire q
+    in every block), so the feature gradient sums over the blocks."""
+    if encoding not in ("vq", "qdi"):
+        raise ValueError(encoding)
+    b = _Builder(n).add("RY", "ALL", "WEIGHT").add("CNOT", "RING")
+    for k in range(blocks):
+        if encoding == "qdi" or k == 0:
+            b.layers.append(L("RZ", "ALL", "INPUT", 0, 1, 0, 0.0))
+            b.nf = max(b.nf, n)
+        else:
+            b.add("RZ", "ALL", "WEIGHT")
+        b.add("RY", "ALL", "WEIGHT").add("CNOT", "RING")
+    return b.layers
+
+
 def circuit_ionq(n, blocks=8):
     """IonQ-style native gates: GPI2(0), RZ(x) encoding, then blocks of
     [GPI, GPI2, MS on brick pairs] (Appendix B, Fig. 11(b))."""
