@@ -700,6 +700,18 @@ __device__ __forceinline__ T seg_sum_dpp(T v, int seg_log) {
   return v;
 }
 
+// Sum over the 64 lanes of the wave, straight-line; valid in lanes 48-63.
+template <typename T>
+__device__ __forceinline__ T wave_sum_dpp(T v) {
+  v = dpp_add<0xB1, 0xF>(v);
+  v = dpp_add<0x4E, 0xF>(v);
+  v = dpp_add<0x141, 0xF>(v);
+  v = dpp_add<0x140, 0xF>(v);
+  v = dpp_add<0x142, 0xA>(v);
+  v = dpp_add<0x143, 0xC>(v);
+  return v;
+}
+
 template <typename T, int K>
 struct Ctx {
   static constexpr int NT = 1 << (K - RB);
@@ -710,7 +722,33 @@ struct Ctx {
   uint32_t base;        // state-index bits of the tile (single-sample mode)
   int seg_log;          // log2 threads per reduction segment
   int units_wg_base;    // unit offset of this workgroup within its sample (single mode)
+  // gradient partials (backward): the thread's slot for accumulator 0, the
+  // distance between accumulators, and whether the thread writes its segment's sum
+  T *pslot;
+  long long pstride;
+  int pwriter;
 };
+
+// Partial slot of the thread: partials[acc_region + (acc * batch + s) * units + u]
+// for the sample s and unit u of the thread's reduction segment.
+template <typename T, int K>
+__device__ __forceinline__ void set_partial_slot(Ctx<T, K> &c, T *partials, long long acc_region, int batch,
+                                                 int units) {
+  const int segm = (1 << c.seg_log) - 1;
+  const int seg = c.tid >> c.seg_log;
+  int s, u;
+  if (c.multi) {
+    const int spt_log = (c.nv - RB) - c.seg_log;   // segments per sample (log2)
+    s = c.sample0 + (seg >> spt_log);
+    u = seg & ((1 << spt_log) - 1);
+  } else {
+    s = c.sample0;
+    u = c.units_wg_base + seg;
+  }
+  c.pwriter = (c.tid & segm) == segm && s < batch;
+  c.pslot = partials ? partials + acc_region + (long long)(s < batch ? s : 0) * units + u : partials;
+  c.pstride = (long long)batch * units;
+}
 
 // Sample of a thread in multi-sample mode: the sample bits are the top thread bits
 // in every stage (register bits are always state bits).
@@ -720,23 +758,40 @@ __device__ __forceinline__ int thread_sample(const Ctx<T, K> &c, int batch) {
   return s < batch ? s : batch - 1;   // padding samples of a ragged last workgroup
 }
 
+// Three sums of consecutive accumulators acc, acc+1, acc+2 (the Pauli sums of
+// one single-qubit gradient): the three reductions interleave, so the DPP
+// steps of one fill the wait states of the others.
+template <typename T, int K>
+__device__ __forceinline__ void write_acc3(const Ctx<T, K> &c, const PassArgs<T> &a, T x, T y, T z, int acc) {
+  if (__builtin_amdgcn_readfirstlane(c.seg_log) == 6) {
+    x = dpp_add<0xB1, 0xF>(x); y = dpp_add<0xB1, 0xF>(y); z = dpp_add<0xB1, 0xF>(z);
+    x = dpp_add<0x4E, 0xF>(x); y = dpp_add<0x4E, 0xF>(y); z = dpp_add<0x4E, 0xF>(z);
+    x = dpp_add<0x141, 0xF>(x); y = dpp_add<0x141, 0xF>(y); z = dpp_add<0x141, 0xF>(z);
+    x = dpp_add<0x140, 0xF>(x); y = dpp_add<0x140, 0xF>(y); z = dpp_add<0x140, 0xF>(z);
+    x = dpp_add<0x142, 0xA>(x); y = dpp_add<0x142, 0xA>(y); z = dpp_add<0x142, 0xA>(z);
+    x = dpp_add<0x143, 0xC>(x); y = dpp_add<0x143, 0xC>(y); z = dpp_add<0x143, 0xC>(z);
+  } else {
+    x = seg_sum_dpp(x, c.seg_log);
+    y = seg_sum_dpp(y, c.seg_log);
+    z = seg_sum_dpp(z, c.seg_log);
+  }
+  if (c.pwriter) {
+    T *p = c.pslot + (long long)acc * c.pstride;
+    p[0] = x;
+    p[c.pstride] = y;
+    p[2 * c.pstride] = z;
+  }
+}
+
 template <typename T, int K>
 __device__ __forceinline__ void write_acc(const Ctx<T, K> &c, const PassArgs<T> &a, T v, int acc) {
-  v = seg_sum_dpp(v, c.seg_log);
-  const int segm = (1 << c.seg_log) - 1;
-  if ((c.tid & segm) == segm) {
-    const int seg = c.tid >> c.seg_log;
-    int s, u;
-    if (c.multi) {
-      const int spt_log = (c.nv - RB) - c.seg_log;   // segments per sample (log2)
-      s = c.sample0 + (seg >> spt_log);
-      u = seg & ((1 << spt_log) - 1);
-    } else {
-      s = c.sample0;
-      u = c.units_wg_base + seg;
-    }
-    if (s < a.batch) a.partials[a.acc_region + ((long long)acc * a.batch + s) * a.units + u] = v;
-  }
+  // one uniform test: whole-wave segments (every single-sample tile) take the
+  // straight-line reduction
+  if (__builtin_amdgcn_readfirstlane(c.seg_log) == 6)
+    v = wave_sum_dpp(v);
+  else
+    v = seg_sum_dpp(v, c.seg_log);
+  if (c.pwriter) c.pslot[(long long)acc * c.pstride] = v;
 }
 
 template <typename T>
@@ -806,9 +861,7 @@ __device__ __forceinline__ void u1g_step(const Ctx<T, K> &c, const PassArgs<T> &
       if (r == 1) u1_grad<T, 1>(vp, vl, sx, sy, sz);
       if (r == 2) u1_grad<T, 2>(vp, vl, sx, sy, sz);
       if (r == 3) u1_grad<T, 3>(vp, vl, sx, sy, sz);
-      write_acc(c, a, sx, ga[r] + 0);
-      write_acc(c, a, sy, ga[r] + 1);
-      write_acc(c, a, sz, ga[r] + 2);
+      write_acc3(c, a, sx, sy, sz, ga[r]);
     }
   }
   u1g_apply<T, MASK, BWD>(vp, m);
@@ -879,9 +932,7 @@ __device__ __forceinline__ void seq_u1(const Ctx<T, K> &c, const PassArgs<T> &a,
     if (ga >= 0) {
       T sx = 0, sy = 0, sz = 0;
       u1_grad<T, R>(vp, vl, sx, sy, sz);
-      write_acc(c, a, sx, ga + 0);
-      write_acc(c, a, sy, ga + 1);
-      write_acc(c, a, sz, ga + 2);
+      write_acc3(c, a, sx, sy, sz, ga);
     }
   }
   u1_apply<T, R, BWD>(vp, m);
@@ -1299,9 +1350,7 @@ __device__ __forceinline__ void run_stage(const Ctx<T, K> &c, const PassArgs<T> 
       if (BWD && (op.flags & F_GRAD)) {
         T sx = 0, sy = 0, sz = 0;
         u1_grad_dispatch(vp, vl, op.r0, sx, sy, sz);
-        write_acc(c, a, sx, op.acc + 0);
-        write_acc(c, a, sy, op.acc + 1);
-        write_acc(c, a, sz, op.acc + 2);
+        write_acc3(c, a, sx, sy, sz, op.acc);
       }
       if (op.kind == OP_U1) {
         cplx<T> m[4];
@@ -1536,6 +1585,10 @@ __attribute__((amdgpu_waves_per_eu(PassOcc<T, BWD, DENSE>::waves))) k_pass(PassA
   }
   const int n = c.n;
   const long long sstride = 1ll << n;
+  c.pslot = nullptr;
+  c.pstride = 0;
+  c.pwriter = 0;
+  if (BWD) set_partial_slot(c, a.partials, a.acc_region, a.batch, a.units);
 
   if (uni(P->n_diag) > 0) build_diag_tables<T, K>(c, a, tab);
 
