@@ -44,6 +44,21 @@ template <typename T>
 __device__ __forceinline__ cplx<T> cjmul(cplx<T> a, cplx<T> b) {
   return cmk(a.x * b.x + a.y * b.y, a.x * b.y - a.y * b.x);
 }
+__device__ __forceinline__ float tfma(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
+__device__ __forceinline__ double tfma(double a, double b, double c) { return __builtin_fma(a, b, c); }
+// s += sg * Im(conj(l) p) and s += sg * Re(conj(l) p) (sg = +-1) as two chained
+// FMAs into the running sum: gradient sums accumulate without separate
+// products and adds
+template <typename T>
+__device__ __forceinline__ void im_acc(T &s, cplx<T> l, cplx<T> p, T sg) {
+  s = tfma(sg * l.x, p.y, s);
+  s = tfma(-sg * l.y, p.x, s);
+}
+template <typename T>
+__device__ __forceinline__ void re_acc(T &s, cplx<T> l, cplx<T> p, T sg) {
+  s = tfma(sg * l.x, p.x, s);
+  s = tfma(sg * l.y, p.y, s);
+}
 template <typename T>
 __device__ __forceinline__ cplx<T> cconj(cplx<T> a) {
   return cmk(a.x, -a.y);
@@ -514,10 +529,12 @@ __device__ __forceinline__ void u1_grad(const cplx<T> (&p)[NREG], const cplx<T> 
   for (int j = 0; j < NREG; ++j) {
     if (j & (1 << R)) continue;
     const cplx<T> pa = p[j], pb = p[j | (1 << R)], la = l[j], lb = l[j | (1 << R)];
-    const cplx<T> u = cjmul(la, pb), w = cjmul(lb, pa);
-    sx += u.y + w.y;
-    sy += w.x - u.x;
-    sz += (la.x * pa.y - la.y * pa.x) - (lb.x * pb.y - lb.y * pb.x);
+    im_acc(sx, la, pb, T(1));    // Im(conj(la) pb) + Im(conj(lb) pa)
+    im_acc(sx, lb, pa, T(1));
+    re_acc(sy, lb, pa, T(1));    // Re(conj(lb) pa) - Re(conj(la) pb)
+    re_acc(sy, la, pb, T(-1));
+    im_acc(sz, la, pa, T(1));    // Im(conj(la) pa) - Im(conj(lb) pb)
+    im_acc(sz, lb, pb, T(-1));
   }
 }
 
@@ -595,9 +612,15 @@ __device__ __forceinline__ T u2s_grad(const cplx<T> (&p)[NREG], const cplx<T> (&
     if (j & ((1 << R0) | (1 << R1))) continue;
     const int i0 = j, i1 = j | (1 << R1), i2 = j | (1 << R0), i3 = j | (1 << R0) | (1 << R1);
     if (XX) {
-      acc += cjmul(l[i0], p[i3]).y + cjmul(l[i3], p[i0]).y + cjmul(l[i1], p[i2]).y + cjmul(l[i2], p[i1]).y;
+      im_acc(acc, l[i0], p[i3], T(1));
+      im_acc(acc, l[i3], p[i0], T(1));
+      im_acc(acc, l[i1], p[i2], T(1));
+      im_acc(acc, l[i2], p[i1], T(1));
     } else {
-      acc += cjmul(l[i0], p[i0]).y - cjmul(l[i1], p[i1]).y - cjmul(l[i2], p[i2]).y + cjmul(l[i3], p[i3]).y;
+      im_acc(acc, l[i0], p[i0], T(1));
+      im_acc(acc, l[i1], p[i1], T(-1));
+      im_acc(acc, l[i2], p[i2], T(-1));
+      im_acc(acc, l[i3], p[i3], T(1));
     }
   }
   return acc;
@@ -628,7 +651,10 @@ __device__ __forceinline__ T u2_grad(const cplx<T> (&p)[NREG], const cplx<T> (&l
     const cplx<T> q2 = pauli_row(cb, 0, p[i2], p[i3], dummy), q3 = pauli_row(cb, 1, p[i2], p[i3], dummy);
     const cplx<T> r0 = pauli_row(ca, 0, q0, q2, dummy), r2 = pauli_row(ca, 1, q0, q2, dummy);
     const cplx<T> r1 = pauli_row(ca, 0, q1, q3, dummy), r3 = pauli_row(ca, 1, q1, q3, dummy);
-    acc += cjmul(l[i0], r0).y + cjmul(l[i1], r1).y + cjmul(l[i2], r2).y + cjmul(l[i3], r3).y;
+    im_acc(acc, l[i0], r0, T(1));
+    im_acc(acc, l[i1], r1, T(1));
+    im_acc(acc, l[i2], r2, T(1));
+    im_acc(acc, l[i3], r3, T(1));
   }
   return acc;
 }
