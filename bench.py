@@ -39,6 +39,7 @@ def parse():
     p.add_argument("--serve-max-qubits", type=int, default=22)
     p.add_argument("--serve-qps-fracs", default="0.5,0.8,0.95")
     p.add_argument("--no-b512", action="store_true")
+    p.add_argument("--no-graph", action="store_true", help="time eager launches instead of a replayed HIP graph")
     # after the timed region, run a plain streaming kernel (float32 negation)
     # over this many MiB three times: the known-size reference that scales
     # rocprofv3's FETCH_SIZE / WRITE_SIZE readings to bytes
@@ -199,6 +200,59 @@ def serving_bench(n_req, n_max, fracs, seed=0, streams=4, budget=160 << 30, heav
                               | {"launches": cb["launches"]},
                               "plain": {k: round(pl[k], 3) for k in ("p50_ms", "p99_ms", "evals_per_s")}})
     return out
+
+
+def time_graph(jobs, steps, warmup):
+    """ms per step with the whole step (every job's forward, <Z_i> and adjoint)
+    captured once as a HIP graph and replayed: no per-kernel launch gaps and
+    no profiling events.  Before and after the timed replays, replays
+    alternate with eager steps and each replay's outputs must equal the eager
+    step's bit for bit (the path is deterministic)."""
+    import torch
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):
+        for j in jobs:
+            j.step()
+    torch.cuda.current_stream().wait_stream(side)
+    torch.cuda.synchronize()
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph):
+        for j in jobs:
+            j.step()
+    outs = [(j.e, j.gw, j.gx) for j in jobs]
+
+    def check(rounds):
+        for _ in range(rounds):
+            graph.replay()
+            torch.cuda.synchronize()
+            got = [tuple(t.clone() for t in o) for o in outs]
+            for j in jobs:
+                j.step()
+            torch.cuda.synchronize()
+            for j, g in zip(jobs, got):
+                for a, b in zip(g, (j.e, j.gw, j.gx)):
+                    if not torch.equal(a, b):
+                        raise RuntimeError(f"graph replay of {j.name} differs from the eager step")
+
+    check(3)
+    for _ in range(warmup):
+        graph.replay()
+    torch.cuda.synchronize()
+    t0 = torch.cuda.Event(enable_timing=True)
+    t1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    wall0 = time.perf_counter()
+    t0.record()
+    for _ in range(steps):
+        graph.replay()
+    t1.record()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - wall0
+    check(1)
+    ms = t0.elapsed_time(t1) / steps
+    del graph
+    return ms, wall / steps * 1e3
 
 
 def dense_sweep(iters=30):
@@ -442,7 +496,12 @@ def main():
         return
 
     jobs = [Job("c4a_16q_b128_ionq", a.mode), Job("c4b_16q_b128_ibm", a.mode)]
-    ms, wall_ms, rep = time_jobs(jobs, a.steps, a.warmup)
+    # per-kernel times: an eager run with the library's HIP events
+    ms_eager, wall_eager, rep = time_jobs(jobs, a.steps, a.warmup)
+    if a.no_graph:
+        ms, wall_ms = ms_eager, wall_eager
+    else:
+        ms, wall_ms = time_graph(jobs, a.steps, a.warmup)
     evals = sum(j.B for j in jobs)
     value = evals / (ms / 1e3)
     out = {
@@ -454,6 +513,10 @@ def main():
         "warmup": a.warmup,
         "ms_per_step": round(ms, 4),
         "wall_ms_per_step": round(wall_ms, 4),
+        "execution": ("eager launches" if a.no_graph else
+                      "one HIP graph per step (both circuits' forward, <Z_i> and adjoint), replayed; "
+                      "replays checked bit for bit against eager steps before and after timing"),
+        "eager_ms_per_step": round(ms_eager, 4),
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,

@@ -279,3 +279,52 @@ def test_rz_ry_cnot_16q_b64_sampled(encoding):
     layers = W.circuit_rz_ry_cnot(n, 8, encoding)
     w, x = W.draw_params(n, layers, B, "normal", 6)
     _sampled_full(f"fig6 {encoding}", [0, 63], spec=(n, B, "c64", layers, w, x))
+
+
+# ------------------------------------------------------- captured graphs --
+
+@pytest.mark.parametrize("name", ["c4a_16q_b128_ionq", "c4b_16q_b128_ibm", "c3_20q_b32"])
+def test_step_graph_replays_equal_eager(name):
+    """Forward, <Z_i> and adjoint captured as one HIP graph (the timed mode of
+    the benchmark): replays alternate with eager steps and program work, each
+    replay equals the eager step bit for bit, and sampled rows match the oracle."""
+    n, B, dt, layers, w, x = W.config(name)
+    B = 8
+    w, x = W.draw_params(n, layers, B, W.CONFIGS[name]["wdist"], W.CONFIGS[name]["seed"])
+    g = W.upstream(B, n, "normal", 3)
+    note(f"case graph {name} B={B}")
+    dev = torch.device("cuda")
+    c = _circuit(n, layers, dt)
+    wt, xt, gt = (torch.tensor(v, device=dev) for v in (w, x, g))
+    st = torch.empty((B, 2 ** n), dtype=c.complex_dtype, device=dev)
+    ws = c.workspace(B, True, dev)
+
+    def step():
+        c.forward(wt, xt, state=st, ws=ws)
+        e = c.expval_z(st, ws=ws)
+        gw, gx = c.adjoint_grad(wt, xt, st, gt, ws=ws)
+        return e, gw, gx
+
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):
+        step()
+    torch.cuda.current_stream().wait_stream(side)
+    torch.cuda.synchronize()
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph):
+        outs = step()
+    for r in range(3):
+        graph.replay()
+        torch.cuda.synchronize()
+        got = [t.clone() for t in outs]
+        _ = torch.randn(1000, device=dev).sum().item()   # program work between replays
+        ref = step()
+        torch.cuda.synchronize()
+        for a, b in zip(got, ref):
+            assert torch.equal(a, b), (name, r)
+    rows = [0, B - 1] if n < 20 else [B - 1]
+    o = oracle_run(n, layers, w, x[rows], g[rows])
+    np.testing.assert_allclose(got[0].cpu().numpy()[rows], o["e"], atol=2e-5)
+    gx = got[2].cpu().numpy()[rows]
+    assert np.max(np.abs(gx - o["gx"])) / np.max(np.abs(o["gx"])) <= 1e-4
