@@ -51,6 +51,8 @@ def parse():
     # instead of the benchmark: time every configuration under each dispatch
     # mode and tile size, one JSON line per case
     p.add_argument("--dispatch-sweep", action="store_true")
+    p.add_argument("--memory-sweep", action="store_true",
+                   help="device memory of one forward + adjoint call vs qubits (QDI circuit)")
     p.add_argument("--vq-qdi-sweep", action="store_true",
                    help="forward/backward/total time vs qubits for the VQ and QDI encodings")
     return p.parse_args()
@@ -390,6 +392,43 @@ def vq_qdi_sweep(iters=20):
                 print(json.dumps(row), flush=True)
 
 
+def memory_sweep():
+    """Fig. 9's measurement on the QDI circuit of Fig. 6 (8 blocks, c64): the
+    device memory of one forward + <Z_i> + adjoint call against the number of
+    qubits at batch 1 and 100.  Reported: the library's workspace query, the
+    state, and the peak the caching allocator saw during the call (all
+    buffers the call needs); beside them, the states a per-layer
+    stored-state backpropagation would keep (computed, (L+1) states)."""
+    import torch
+    import workloads as W
+    from paper_2506_04891_amd import tqsim as T
+    dev = torch.device("cuda")
+    for B in (1, 100):
+        for n in range(4, 23, 2):
+            layers = W.circuit_rz_ry_cnot(n, 8, "qdi")
+            c = T.Circuit(n, layers, "c64")
+            w, x = W.draw_params(n, layers, B, "normal", 0)
+            torch.cuda.synchronize()
+            torch.cuda.empty_cache()
+            torch.cuda.reset_peak_memory_stats()
+            base = torch.cuda.memory_allocated()
+            wt, xt = torch.tensor(w, device=dev), torch.tensor(x, device=dev)
+            g = torch.ones((B, n), dtype=torch.float64, device=dev)
+            st = torch.empty((B, 2 ** n), dtype=c.complex_dtype, device=dev)
+            ws = c.workspace(B, True, dev)
+            c.forward(wt, xt, state=st, ws=ws)
+            e = c.expval_z(st, ws=ws)
+            gw, gx = c.adjoint_grad(wt, xt, st, g, ws=ws)
+            torch.cuda.synchronize()
+            peak = torch.cuda.max_memory_allocated() - base
+            state = B * (8 << n)
+            print(json.dumps({"encoding": "qdi", "batch": B, "n": n, "layers": len(layers),
+                              "state_bytes": state, "workspace_bytes": c.workspace_size(B, True),
+                              "peak_bytes": int(peak),
+                              "stored_state_backprop_bytes": (len(layers) + 1) * state}), flush=True)
+            del wt, xt, g, st, ws, e, gw, gx, c
+
+
 def _oracle_samples(samples, seed_offset=0, keep=None):
     """Seconds the oracle (numpy complex128, one BLAS thread) takes for forward
     <Z_i> + adjoint gradients of `samples` rows of each 16-qubit circuit.
@@ -476,7 +515,7 @@ def main():
     # the CPU baselines run first: the pooled one forks, which must happen
     # before anything initialises the GPU in this process
     oracle_rows = {}
-    sweep = a.dense_sweep or a.dispatch_sweep or a.vq_qdi_sweep
+    sweep = a.dense_sweep or a.dispatch_sweep or a.vq_qdi_sweep or a.memory_sweep
     cpu = None if (a.no_cpu_baseline or sweep) else cpu_baseline(keep=oracle_rows)
     cpu_pool = None if (a.no_cpu_baseline or sweep) else cpu_baseline_pool()
     import torch
@@ -493,6 +532,9 @@ def main():
         return
     if a.vq_qdi_sweep:
         vq_qdi_sweep()
+        return
+    if a.memory_sweep:
+        memory_sweep()
         return
 
     jobs = [Job("c4a_16q_b128_ionq", a.mode), Job("c4b_16q_b128_ibm", a.mode)]
