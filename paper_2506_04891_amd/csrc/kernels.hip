@@ -714,6 +714,59 @@ __device__ __forceinline__ double dpp_add(double v) {
   return v + __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
 }
 
+template <int CTRL>
+__device__ __forceinline__ float dpp_mov(float v) {
+  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, 0xF, 0xF, true));
+}
+template <int CTRL>
+__device__ __forceinline__ double dpp_mov(double v) {
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_update_dpp(0, (int)(b & 0xffffffffll), CTRL, 0xF, 0xF, true);
+  const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), CTRL, 0xF, 0xF, true);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
+}
+
+// v + v of lane ^ 16 and v + v of lane ^ 32 with the CDNA4 row swaps: with both
+// operands equal, the two results of a swap hold each lane's value and its
+// partner's, in some order per lane, so their sum is the pair sum everywhere.
+__device__ __forceinline__ float xor16_add(float v) {
+  const auto r = __builtin_amdgcn_permlane16_swap(__float_as_uint(v), __float_as_uint(v), false, false);
+  return __uint_as_float(r[0]) + __uint_as_float(r[1]);
+}
+__device__ __forceinline__ float xor32_add(float v) {
+  const auto r = __builtin_amdgcn_permlane32_swap(__float_as_uint(v), __float_as_uint(v), false, false);
+  return __uint_as_float(r[0]) + __uint_as_float(r[1]);
+}
+__device__ __forceinline__ double xor16_add(double v) {
+  const long long b = __double_as_longlong(v);
+  const auto lo = __builtin_amdgcn_permlane16_swap((unsigned)b, (unsigned)b, false, false);
+  const auto hi = __builtin_amdgcn_permlane16_swap((unsigned)(b >> 32), (unsigned)(b >> 32), false, false);
+  return __longlong_as_double(((long long)hi[0] << 32) | lo[0]) + __longlong_as_double(((long long)hi[1] << 32) | lo[1]);
+}
+__device__ __forceinline__ double xor32_add(double v) {
+  const long long b = __double_as_longlong(v);
+  const auto lo = __builtin_amdgcn_permlane32_swap((unsigned)b, (unsigned)b, false, false);
+  const auto hi = __builtin_amdgcn_permlane32_swap((unsigned)(b >> 32), (unsigned)(b >> 32), false, false);
+  return __longlong_as_double(((long long)hi[0] << 32) | lo[0]) + __longlong_as_double(((long long)hi[1] << 32) | lo[1]);
+}
+
+// Three sums reduced over the 64 lanes of the wave as one transposed tree: the
+// first two butterfly steps halve the number of values per lane (a lane keeps
+// the value selected by its two low lane bits), the rest reduce that one value.
+// Afterwards lane l holds the total of value l & 3 (x, y, z, 0).
+template <typename T>
+__device__ __forceinline__ T wave_sum3_transposed(T x, T y, T z, int lane) {
+  const bool b0 = lane & 1, b1 = lane & 2;
+  const T p = (b0 ? y : x) + dpp_mov<0xB1>(b0 ? x : y);        // quad_perm [1,0,3,2]
+  const T q = (b0 ? T(0) : z) + dpp_mov<0xB1>(b0 ? z : T(0));
+  T v = (b1 ? q : p) + dpp_mov<0x4E>(b1 ? p : q);               // quad_perm [2,3,0,1]
+  v += dpp_mov<0x124>(v);                                        // row_ror:4
+  v += dpp_mov<0x128>(v);                                        // row_ror:8
+  v = xor16_add(v);
+  v = xor32_add(v);
+  return v;
+}
+
 // Sum over aligned segments of 2^seg_log lanes; valid in the last lane of each segment.
 template <typename T>
 __device__ __forceinline__ T seg_sum_dpp(T v, int seg_log) {
@@ -753,6 +806,9 @@ struct Ctx {
   T *pslot;
   long long pstride;
   int pwriter;
+  // whole-wave segments: lanes 0-2 write the three sums of a transposed reduction
+  T *pslot3;
+  int pwriter3;
 };
 
 // Partial slot of the thread: partials[acc_region + (acc * batch + s) * units + u]
@@ -774,6 +830,8 @@ __device__ __forceinline__ void set_partial_slot(Ctx<T, K> &c, T *partials, long
   c.pwriter = (c.tid & segm) == segm && s < batch;
   c.pslot = partials ? partials + acc_region + (long long)(s < batch ? s : 0) * units + u : partials;
   c.pstride = (long long)batch * units;
+  c.pwriter3 = (c.tid & 63) < 3 && s < batch;
+  c.pslot3 = partials ? c.pslot + (long long)(c.tid & 3) * c.pstride : partials;
 }
 
 // Sample of a thread in multi-sample mode: the sample bits are the top thread bits
@@ -785,17 +843,13 @@ __device__ __forceinline__ int thread_sample(const Ctx<T, K> &c, int batch) {
 }
 
 // Three sums of consecutive accumulators acc, acc+1, acc+2 (the Pauli sums of
-// one single-qubit gradient): the three reductions interleave, so the DPP
-// steps of one fill the wait states of the others.
+// one single-qubit gradient), reduced together.
 template <typename T, int K>
 __device__ __forceinline__ void write_acc3(const Ctx<T, K> &c, const PassArgs<T> &a, T x, T y, T z, int acc) {
   if (__builtin_amdgcn_readfirstlane(c.seg_log) == 6) {
-    x = dpp_add<0xB1, 0xF>(x); y = dpp_add<0xB1, 0xF>(y); z = dpp_add<0xB1, 0xF>(z);
-    x = dpp_add<0x4E, 0xF>(x); y = dpp_add<0x4E, 0xF>(y); z = dpp_add<0x4E, 0xF>(z);
-    x = dpp_add<0x141, 0xF>(x); y = dpp_add<0x141, 0xF>(y); z = dpp_add<0x141, 0xF>(z);
-    x = dpp_add<0x140, 0xF>(x); y = dpp_add<0x140, 0xF>(y); z = dpp_add<0x140, 0xF>(z);
-    x = dpp_add<0x142, 0xA>(x); y = dpp_add<0x142, 0xA>(y); z = dpp_add<0x142, 0xA>(z);
-    x = dpp_add<0x143, 0xC>(x); y = dpp_add<0x143, 0xC>(y); z = dpp_add<0x143, 0xC>(z);
+    const T v = wave_sum3_transposed(x, y, z, c.lane);
+    if (c.pwriter3) c.pslot3[(long long)acc * c.pstride] = v;
+    return;
   } else {
     x = seg_sum_dpp(x, c.seg_log);
     y = seg_sum_dpp(y, c.seg_log);
