@@ -259,12 +259,20 @@ double op_flops(const DevOp &o) {
 // Dense op: 2^nv complex multiply-adds per amplitude.
 double dense_flops(int nv) { return 8.0 * (double)(1 << nv); }
 
+// Gradient sums per amplitude.  A Pauli sum Im<l|P|p> needs one real term per
+// amplitude, l.x p.y - l.y p.x (or the real part for Y): two multiplies, one
+// add and the accumulation, 4 flops.  A single-qubit gate takes three sums, a
+// pair gate one; a diagonal layer takes w = Im(conj(l) p) (3 flops) and its
+// parity sums by a 16-point Walsh-Hadamard transform (4 adds per amplitude).
+constexpr double GRAD_U1_FLOPS = 12.0, GRAD_U2_FLOPS = 4.0, GRAD_DIAG_FLOPS = 7.0;
+
 // Backward flops of an op per amplitude: psi and lambda are both uncomputed
-// (2x forward) and ops with parameters add their gradient sums (U1: three
-// Pauli sums over pairs, 6 flops per amplitude each; U2 / diagonal: one sum).
+// (2x forward; a diagonal layer's phase is formed once for both, 6 + 2 x 6)
+// and ops with parameters add their gradient sums.
 double op_flops_bwd(const DevOp &o) {
+  if (o.kind == OP_DIAG) return 18.0 + ((o.flags & F_GRAD) ? GRAD_DIAG_FLOPS : 0.0);
   double f = 2.0 * op_flops(o);
-  if (o.flags & F_GRAD) f += (o.kind == OP_U1) ? 18.0 : 8.0;
+  if (o.flags & F_GRAD) f += (o.kind == OP_U1) ? GRAD_U1_FLOPS : GRAD_U2_FLOPS;
   return f;
 }
 
@@ -322,26 +330,27 @@ tqs_status launch_pass(tqs_circuit *c, int pi, int B, const cplx<T> *src0, cplx<
             if (q.mat[k] < 0) continue;
             const bool pair = k < 2 || k == 6;
             if (pair)
-              f += BWD ? 12.0 + (q.acc[k] >= 0 ? 8.0 : 0.0) : 6.0;
+              f += BWD ? 12.0 + (q.acc[k] >= 0 ? GRAD_U2_FLOPS : 0.0) : 6.0;
             else
-              f += BWD ? 28.0 + (q.acc[k] >= 0 ? 18.0 : 0.0) : 14.0;
+              f += BWD ? 28.0 + (q.acc[k] >= 0 ? GRAD_U1_FLOPS : 0.0) : 14.0;
           }
         } else if (P.dop[oi].kind == OP_U2G) {
-          // two structured pair gates (6 flop/amp each); MS gradients 8 each
+          // two structured pair gates (6 flop/amp each) and their gradient sums
           const DevGroup &g = P.dgroup[P.dop[oi].aux];
-          for (int r = 0; r < 2; ++r) f += BWD ? 12.0 + (g.acc[r] >= 0 ? 8.0 : 0.0) : 6.0;
+          for (int r = 0; r < 2; ++r) f += BWD ? 12.0 + (g.acc[r] >= 0 ? GRAD_U2_FLOPS : 0.0) : 6.0;
         } else if (P.dop[oi].kind == OP_U1G) {
           // each member: a complex 2x2 (14 flop/amp), backward twice that plus
           // its Pauli sums when it has parameters
           const DevGroup &g = P.dgroup[P.dop[oi].aux];
           for (int r = 0; r < RB; ++r)
-            if (g.mat[r] >= 0) f += BWD ? 28.0 + (g.acc[r] >= 0 ? 18.0 : 0.0) : 14.0;
+            if (g.mat[r] >= 0) f += BWD ? 28.0 + (g.acc[r] >= 0 ? GRAD_U1_FLOPS : 0.0) : 14.0;
         } else
           f += BWD ? op_flops_bwd(P.dop[oi]) : op_flops(P.dop[oi]);
       }
     if (BWD)
       for (int st = d.grad_stage_begin; st < d.grad_stage_begin + d.n_grad_stages; ++st)
-        f += 18.0 * (P.dstage[st].op_end - P.dstage[st].op_begin);
+        for (int oi = P.dstage[st].op_begin; oi < P.dstage[st].op_end; ++oi)
+          f += P.dop[oi].kind == OP_GRAD1 ? GRAD_U1_FLOPS : GRAD_U2_FLOPS;
     flops = amps * f;
   }
   ProfScope ps(c, s, std::string(BWD ? "pass_bwd_K" : "pass_fwd_K") + std::to_string(d.K) +
