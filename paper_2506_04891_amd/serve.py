@@ -283,7 +283,7 @@ class Server:
                 try:
                     self.ex.wait(self._inflight[0].handle)
                 except Exception:
-                    pass
+                    pass   # the same error surfaces from results() and fails the group there
             else:
                 time.sleep(self.poll_s)
 
