@@ -1341,7 +1341,7 @@ __device__ __forceinline__ void dense_stage(const Ctx<T, K> &c, cplx<T> *Lp, cpl
   if (BWD) dense_apply<T, K, NV, true>(c, Ll, scr, U);
 }
 
-template <typename T, int K, bool BWD, bool DENSE>
+template <typename T, int K, bool BWD, bool DENSE, bool DIAG>
 __device__ __forceinline__ void run_stage(const Ctx<T, K> &c, const PassArgs<T> &a, const UStage &S, cplx<T> *Lp,
                           cplx<T> *Ll, const cplx<T> *tab, bool grad_only) {
   constexpr int NT = Ctx<T, K>::NT;
@@ -1489,7 +1489,7 @@ __device__ __forceinline__ void run_stage(const Ctx<T, K> &c, const PassArgs<T> 
                                                 : u2s_grad_dispatch<T, false>(vp, vl, op.r0, op.r1);
         write_acc(c, a, g, op.acc);
       }
-    } else if (op.kind == OP_DIAG) {
+    } else if (DIAG && op.kind == OP_DIAG) {
       kptr<DevDiag> dg = a.diags + uni(a.pass->diag_begin) + op.aux;
       const DiagView dv = diag_view(dg);
       if (BWD && (op.flags & F_GRAD)) {
@@ -1630,7 +1630,9 @@ struct PassOcc {
   static constexpr int waves = (sizeof(T) != 4 || DENSE) ? 1 : (BWD ? 2 : 3);
 };
 
-template <typename T, int K, bool BWD, bool DENSE>
+// DIAG = false: the variant for passes without diagonal layers (no phase
+// tables, no diagonal op code).
+template <typename T, int K, bool BWD, bool DENSE, bool DIAG>
 __global__ void __launch_bounds__(1 << (K - RB))
 __attribute__((amdgpu_waves_per_eu(PassOcc<T, BWD, DENSE>::waves))) k_pass(PassArgs<T> a) {
   constexpr int NT = 1 << (K - RB);
@@ -1670,7 +1672,7 @@ __attribute__((amdgpu_waves_per_eu(PassOcc<T, BWD, DENSE>::waves))) k_pass(PassA
   c.pwriter = 0;
   if (BWD) set_partial_slot(c, a.partials, a.acc_region, a.batch, a.units);
 
-  if (uni(P->n_diag) > 0) build_diag_tables<T, K>(c, a, tab);
+  if (DIAG && uni(P->n_diag) > 0) build_diag_tables<T, K>(c, a, tab);
 
   // ---------------- load ----------------
   // Element e = tid + i * NT has tile index e; tile bits 0..K-RB-1 come from
@@ -1873,13 +1875,13 @@ __attribute__((amdgpu_waves_per_eu(PassOcc<T, BWD, DENSE>::waves))) k_pass(PassA
   const int ns = uni(P->n_stages), sb = uni(P->stage_begin);
   for (int si = 0; si < ns; ++si) {
     const UStage S = load_stage(a.stages + sb + (BWD ? (ns - 1 - si) : si));
-    run_stage<T, K, BWD, DENSE>(c, a, S, Lp, Ll, tab, false);
+    run_stage<T, K, BWD, DENSE, DIAG>(c, a, S, Lp, Ll, tab, false);
   }
   if (BWD) {
     const int ng = uni(P->n_grad_stages), gsb = uni(P->grad_stage_begin);
     for (int si = 0; si < ng; ++si) {
       const UStage S = load_stage(a.stages + gsb + si);
-      run_stage<T, K, BWD, DENSE>(c, a, S, Lp, Ll, tab, true);
+      run_stage<T, K, BWD, DENSE, DIAG>(c, a, S, Lp, Ll, tab, true);
     }
     const uint32_t omask = uniu(P->outside_mask);
     if (omask && !c.multi) outside_embed_grads(c, a, P, Ll, omask);

@@ -10,12 +10,18 @@ namespace tqs {
 template <typename T>
 struct PassArgs;
 
-// Launch k_pass<T, K, BWD, dense> (dense: the matrix-core variant, K = 10 only).
-// Returns false for a tile size that is not built.
-bool launch_pass_f32_fwd(const PassArgs<float> &a, int K, bool dense, int grid, size_t lds, hipStream_t s);
-bool launch_pass_f32_bwd(const PassArgs<float> &a, int K, bool dense, int grid, size_t lds, hipStream_t s);
-bool launch_pass_f64_fwd(const PassArgs<double> &a, int K, bool dense, int grid, size_t lds, hipStream_t s);
-bool launch_pass_f64_bwd(const PassArgs<double> &a, int K, bool dense, int grid, size_t lds, hipStream_t s);
+// Launch k_pass<T, K, BWD, dense, diag> (dense: the matrix-core variant, K = 10
+// only; diag = false, the variant without diagonal layers, is built for K = 12
+// and the other sizes use the diag variant).  Returns false for a tile size
+// that is not built.
+bool launch_pass_f32_fwd(const PassArgs<float> &a, int K, bool dense, bool diag, int grid, size_t lds,
+                         hipStream_t s);
+bool launch_pass_f32_bwd(const PassArgs<float> &a, int K, bool dense, bool diag, int grid, size_t lds,
+                         hipStream_t s);
+bool launch_pass_f64_fwd(const PassArgs<double> &a, int K, bool dense, bool diag, int grid, size_t lds,
+                         hipStream_t s);
+bool launch_pass_f64_bwd(const PassArgs<double> &a, int K, bool dense, bool diag, int grid, size_t lds,
+                         hipStream_t s);
 
 // Allow the kernels of one unit the full 160 KiB of LDS.
 void pass_attrs_f32_fwd();
@@ -27,26 +33,26 @@ template <typename T, bool BWD>
 struct PassLaunch;
 template <>
 struct PassLaunch<float, false> {
-  static bool run(const PassArgs<float> &a, int K, bool d, int g, size_t l, hipStream_t s) {
-    return launch_pass_f32_fwd(a, K, d, g, l, s);
+  static bool run(const PassArgs<float> &a, int K, bool d, bool dg, int g, size_t l, hipStream_t s) {
+    return launch_pass_f32_fwd(a, K, d, dg, g, l, s);
   }
 };
 template <>
 struct PassLaunch<float, true> {
-  static bool run(const PassArgs<float> &a, int K, bool d, int g, size_t l, hipStream_t s) {
-    return launch_pass_f32_bwd(a, K, d, g, l, s);
+  static bool run(const PassArgs<float> &a, int K, bool d, bool dg, int g, size_t l, hipStream_t s) {
+    return launch_pass_f32_bwd(a, K, d, dg, g, l, s);
   }
 };
 template <>
 struct PassLaunch<double, false> {
-  static bool run(const PassArgs<double> &a, int K, bool d, int g, size_t l, hipStream_t s) {
-    return launch_pass_f64_fwd(a, K, d, g, l, s);
+  static bool run(const PassArgs<double> &a, int K, bool d, bool dg, int g, size_t l, hipStream_t s) {
+    return launch_pass_f64_fwd(a, K, d, dg, g, l, s);
   }
 };
 template <>
 struct PassLaunch<double, true> {
-  static bool run(const PassArgs<double> &a, int K, bool d, int g, size_t l, hipStream_t s) {
-    return launch_pass_f64_bwd(a, K, d, g, l, s);
+  static bool run(const PassArgs<double> &a, int K, bool d, bool dg, int g, size_t l, hipStream_t s) {
+    return launch_pass_f64_bwd(a, K, d, dg, g, l, s);
   }
 };
 

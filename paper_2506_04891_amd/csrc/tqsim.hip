@@ -357,7 +357,7 @@ tqs_status launch_pass(tqs_circuit *c, int pi, int B, const cplx<T> *src0, cplx<
                          (sizeof(T) == 8 ? "_c128" : "_c64"), bytes, flops);
   // passes holding full-layer matrix ops use their own instantiation, so that
   // the matrix-core code does not raise the register use of the others
-  if (!PassLaunch<T, BWD>::run(a, d.K, d.dense_off >= 0, grid, lds, s))
+  if (!PassLaunch<T, BWD>::run(a, d.K, d.dense_off >= 0, d.n_diag > 0, grid, lds, s))
     return fail(TQS_EUNSUPPORTED, d.dense_off >= 0 ? "dense layers need a 10-bit tile" : "tile size not built");
   ps.end();
   HIP_TRY(hipGetLastError());

@@ -8,7 +8,7 @@
 
     python -m paper_2506_04891_amd.rocprof_summary traffic --fetch F.db --write W.db \
         --kernel SUBSTR --copy-kernel SUBSTR --copy-bytes N --command-fetch "..." --command-write "..."
-        HBM bytes per launch of one kernel from FETCH_SIZE / WRITE_SIZE counter
+        HBM bytes per launch of the kernels matching SUBSTR (pooled) from FETCH_SIZE / WRITE_SIZE counter
         runs, each scaled by what the same counter reads for a plain streaming
         kernel that moves a known number of bytes in the same run
 
@@ -113,13 +113,22 @@ def _pick(per_kernel, sub):
     return keys[0], per_kernel[keys[0]]
 
 
+def _pick_all(per_kernel, sub):
+    """Every kernel whose name contains `sub` (e.g. all template variants of
+    one pass kind), with their dispatches pooled."""
+    keys = sorted(k for k in per_kernel if sub in k)
+    if not keys:
+        raise SystemExit(f"kernel substring {sub!r} matches nothing")
+    return " + ".join(keys), [v for k in keys for v in per_kernel[k]]
+
+
 def traffic_summary(a):
     fetch = _counter(a.fetch, "FETCH_SIZE")
     write = _counter(a.write, "WRITE_SIZE")
     ck, cf = _pick(fetch, a.copy_kernel)
     _, cw = _pick(write, a.copy_kernel)
-    kk, kf = _pick(fetch, a.kernel)
-    _, kw = _pick(write, a.kernel)
+    kk, kf = _pick_all(fetch, a.kernel)
+    _, kw = _pick_all(write, a.kernel)
     kib = a.copy_bytes / 1024.0
     cf_avg, cw_avg = sum(cf) / len(cf), sum(cw) / len(cw)
     f_fac, w_fac = kib / cf_avg, kib / cw_avg
