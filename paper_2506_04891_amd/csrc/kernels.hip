@@ -672,6 +672,7 @@ struct PassArgs {
   kptr<DevPerm> perms;
   kptr<DevGroup> groups;
   kptr<DevSeq> seqs;
+  kptr<DevTermGrad> tgrads;
   kptr<cplx<T>> mats;
   kptr<cplx<T>> mats_ps;
   int mats_ps_stride;
@@ -1498,28 +1499,13 @@ __device__ __forceinline__ void run_stage(const Ctx<T, K> &c, const PassArgs<T> 
 #pragma unroll
         for (int j = 0; j < NREG; ++j) w[j] = vl[j].x * vp[j].y - vl[j].y * vp[j].x;
         wht16(w);
-        const int tbeg = uni(dg->term_begin), tend = uni(dg->term_end);
-        for (int ti = tbeg; ti < tend; ++ti) {
-          kptr<DevTerm> tm = a.terms + ti;
-          const int tacc = uni(tm->acc);
-          if (tacc < 0) continue;
-          int m = 0;
-          int neg = 0;
-          const int nb = uni(tm->nbits);
-          for (int q = 0; q < nb; ++q) {
-            const int tb = uni(tm->tb[q]);
-            if (tb < 0) {
-              neg ^= (c.base >> uni(tm->gb[q])) & 1;
-            } else {
-              int rk = -1;
-              for (int k = 0; k < RB; ++k)
-                if (S.rbits[k] == tb) rk = k;
-              if (rk >= 0)
-                m |= 1 << rk;
-              else
-                neg ^= (tt >> tb) & 1;
-            }
-          }
+        // one entry per term with a parameter, laid out by the planner for this
+        // stage: the parity-sum index m and the sign masks
+        for (int k = 0; k < op.r1; ++k) {
+          kptr<DevTermGrad> tg = a.tgrads + op.mat + k;
+          const int tacc = uni(tg->acc), m = uni(tg->m);
+          const uint32_t tmask = uniu(tg->tmask), gmask = uniu(tg->gmask);
+          const int neg = (__builtin_popcount(c.base & gmask) + __builtin_popcount((uint32_t)tt & tmask)) & 1;
           T val = wht_pick(w, m);
           if (neg) val = -val;
           write_acc(c, a, val, tacc);

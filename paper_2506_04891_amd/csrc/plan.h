@@ -98,6 +98,18 @@ struct DevTerm {
   int32_t tab;            // 0: TL, 1: TH, 2: constant
 };
 
+// Gradient of one diagonal term as its op runs in one stage: the accumulator,
+// the term's in-register bits as a register-bit pattern m (the index of its
+// parity sum in the Walsh-Hadamard transform of the thread's 16 values), and
+// the masks whose parities give the sign: tile bits held by the thread index
+// (tmask, tile-bit positions) and bits outside the tile (gmask, state-index
+// bits).  An OP_DIAG op with gradients lists its terms' entries from index
+// mat, r1 of them.
+struct DevTermGrad {
+  int32_t acc, m;
+  uint32_t tmask, gmask;
+};
+
 // Members of an OP_U1G group, by register bit: matrix offset and first gradient
 // accumulator (3 per gate: the X, Y, Z Pauli sums), -1 when the bit has no gate
 // or the gate no parameter.  OP_U2G uses slots 0 and 1 for its two pairs (one

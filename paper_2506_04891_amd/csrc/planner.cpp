@@ -950,6 +950,7 @@ static std::string emit(Plan &P) {
   P.dop.clear();
   P.ddiag.clear();
   P.dterm.clear();
+  P.dtgrad.clear();
   P.dperm.clear();
   P.dgroup.clear();
   P.dseq.clear();
@@ -1257,6 +1258,33 @@ static std::string emit(Plan &P) {
         }
         o.aux = diag_index[oi_ir];
         o.flags = op.has_grad ? F_GRAD : 0;
+        // per-stage gradient entries of the terms that have parameters
+        o.mat = (int)P.dtgrad.size();
+        o.r1 = 0;
+        {
+          const DevDiag &dg = P.ddiag[d.diag_begin + o.aux];
+          for (int ti = dg.term_begin; ti < dg.term_end; ++ti) {
+            const DevTerm &dt = P.dterm[ti];
+            if (dt.acc < 0) continue;
+            DevTermGrad g;
+            g.acc = dt.acc;
+            g.m = 0;
+            g.tmask = g.gmask = 0;
+            for (int q = 0; q < dt.nbits; ++q) {
+              if (dt.tb[q] < 0) {
+                g.gmask |= 1u << dt.gb[q];
+              } else {
+                const int rk = ridx(dt.tb[q]);
+                if (rk >= 0)
+                  g.m |= 1 << rk;
+                else
+                  g.tmask |= 1u << dt.tb[q];
+              }
+            }
+            P.dtgrad.push_back(g);
+            ++o.r1;
+          }
+        }
       } else if (op.kind == IR_DENSE) {
         o.kind = OP_DENSE;
         o.mat = op_mat[oi_ir];

@@ -71,6 +71,7 @@ struct Plan {
   std::vector<DevOp> dop;
   std::vector<DevDiag> ddiag;
   std::vector<DevTerm> dterm;
+  std::vector<DevTermGrad> dtgrad;
   std::vector<DevPerm> dperm;
   std::vector<DevGroup> dgroup;
   std::vector<DevSeq> dseq;

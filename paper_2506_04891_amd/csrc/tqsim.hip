@@ -68,6 +68,7 @@ struct tqs_circuit {
   DevPerm *d_perm = nullptr;
   DevGroup *d_group = nullptr;
   DevSeq *d_seq = nullptr;
+  DevTermGrad *d_tgrad = nullptr;
   PrepItem *d_prep = nullptr;
   Factor *d_fac = nullptr;
   Contrib *d_contrib = nullptr;
@@ -123,6 +124,7 @@ tqs_status upload(tqs_circuit *c) {
       {P.dperm.data(), bytes_of(P.dperm), (void **)&c->d_perm},
       {P.dgroup.data(), bytes_of(P.dgroup), (void **)&c->d_group},
       {P.dseq.data(), bytes_of(P.dseq), (void **)&c->d_seq},
+      {P.dtgrad.data(), bytes_of(P.dtgrad), (void **)&c->d_tgrad},
       {P.prep.data(), bytes_of(P.prep), (void **)&c->d_prep},
       {P.factors.data(), bytes_of(P.factors), (void **)&c->d_fac},
       {P.contribs.data(), bytes_of(P.contribs), (void **)&c->d_contrib},
@@ -292,6 +294,7 @@ tqs_status launch_pass(tqs_circuit *c, int pi, int B, const cplx<T> *src0, cplx<
   a.perms = kc(c->d_perm);
   a.groups = kc(c->d_group);
   a.seqs = kc(c->d_seq);
+  a.tgrads = kc(c->d_tgrad);
   a.mats = kc(reinterpret_cast<const cplx<T> *>(ws + L.mats));
   a.mats_ps = kc(reinterpret_cast<const cplx<T> *>(ws + L.mats_ps));
   a.mats_ps_stride = P.n_mats_ps;
