@@ -456,7 +456,7 @@ def _pool_worker(k, per_worker):
     return _oracle_samples(per_worker, seed_offset=k * per_worker)
 
 
-def cpu_baseline(sample=4, keep=None):
+def cpu_baseline(sample=12, keep=None):
     """The oracle on `sample` rows of each 16-qubit circuit, one thread."""
     t = _oracle_samples(sample, keep=keep)
     evals = 2 * sample
@@ -491,7 +491,7 @@ def errors_vs_oracle(jobs, ref):
     return out
 
 
-def cpu_baseline_pool(per_worker=2):
+def cpu_baseline_pool(per_worker=6):
     """The same oracle over a process pool (one process per core, one thread
     each; at most 16 cores), parallel over samples.  Run before the GPU is
     initialised: the pool forks this process."""
