@@ -44,3 +44,30 @@ def test_input_generators_import_neither_side():
     for path in _sources("workloads"):
         text = open(path).read()
         assert not re.search(r"^\s*(from|import)\s+(oracle|paper_2506_04891_amd)\b", text, re.M), path
+
+
+def test_bench_refuses_more_than_one_gpu():
+    """The benchmark runs on one GPU; asking for more ends with a message."""
+    import json
+    import subprocess
+    import sys
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"],
+                       capture_output=True, text=True, timeout=120)
+    assert r.returncode == 2
+    line = json.loads(r.stdout.strip().splitlines()[-1])
+    assert line["n_gpus"] == 2 and "one GPU" in line["error"]
+
+
+def test_committed_code_does_not_use_working_files():
+    """Nothing committed imports, reads or runs a file of the scratch folder."""
+    import subprocess
+    files = subprocess.run(["git", "-C", ROOT, "ls-files"], capture_output=True, text=True).stdout.split()
+    pat = re.compile(r"_work[/\\]")
+    bad = []
+    for f in files:
+        if not f.endswith((".py", ".hip", ".cpp", ".h", ".inc", ".sh", ".toml", ".cfg")):
+            continue
+        with open(os.path.join(ROOT, f), errors="replace") as fh:
+            if pat.search(fh.read()):
+                bad.append(f)
+    assert not bad, bad
