@@ -297,16 +297,21 @@ def grad_param_shift(n, layers, weights, features, g):
     """Two-term parameter shift, exact for gates exp(-i a P) with P^2 = I:
     rotations and ZZ: [f(t + pi/2) - f(t - pi/2)] / 2;
     MS(t) = exp(-i pi t XX): pi [f(t + 1/4) - f(t - 1/4)].
-    Parameters of GPI / GPI2 layers are left as NaN (no two-term rule)."""
+    Parameters of GPI / GPI2 layers are left as NaN (no two-term rule), and
+    so is every parameter that more than one gate reads (a feature re-uploaded
+    in several layers): the two-term rule is exact only for a parameter that
+    enters the circuit once."""
     nw, nf = param_counts(n, layers)
     gw = np.full(len(weights), np.nan)
     gx = np.full(features.shape, np.nan)
     kind_w, kind_x = {}, {}
     for inst in expand(n, layers):
         if inst[2] == "WEIGHT":
-            kind_w[inst[3]] = inst[0]
+            kind_w.setdefault(inst[3], []).append(inst[0])
         elif inst[2] == "INPUT":
-            kind_x[inst[3]] = inst[0]
+            kind_x.setdefault(inst[3], []).append(inst[0])
+    kind_w = {i: g[0] for i, g in kind_w.items() if len(g) == 1}
+    kind_x = {i: g[0] for i, g in kind_x.items() if len(g) == 1}
     for i, gate in kind_w.items():
         if gate not in _SHIFT:
             continue

@@ -129,13 +129,32 @@ def test_rz_layer_eigenphase(n):
 
 @pytest.mark.parametrize("n", [3, 4, 6])
 def test_zz_ring_uses_k_rzz(n):
-    """Rzz ring (with the (n-1, 0) pair) = psi o exp(-(i/2) K_Rzz theta) (Sec. 2.4.1)."""
+    """Rzz ring (with the (n-1, 0) pair) = psi o exp(-(i/2) K_Rzz theta)
+    (Sec. 2.4.1, with Appendix A's sign): the oracle's K_Rzz builder against
+    the ring applied gate by gate (O2) and as its Kronecker-built layer
+    matrix (O1), both of which use only Appendix A's Rzz matrix."""
     th = RNG.standard_normal(n)
-    K = sim.k_rz(n)
-    Kzz = np.stack([K[:, j] * K[:, (j + 1) % n] for j in range(n)], axis=1)
+    Kzz = sim.k_rzz_ring(n)
+    assert Kzz.shape == (2 ** n, n) and set(np.unique(Kzz)) <= {-1, 1}
     psi = _rand_state(2, n, 2)
-    out = sim.run_o2(n, [W.L("ZZ", "RING", "WEIGHT")], th, np.zeros((2, 0)), psi0=psi)
-    np.testing.assert_allclose(out, psi * np.exp(-0.5j * (Kzz @ th))[None], atol=1e-14)
+    ref = psi * np.exp(-0.5j * (Kzz @ th))[None]
+    layers = [W.L("ZZ", "RING", "WEIGHT")]
+    out = sim.run_o2(n, layers, th, np.zeros((2, 0)), psi0=psi)
+    np.testing.assert_allclose(out, ref, atol=1e-14)
+    U = sim.layer_unitary(n, layers, 0, th, None)
+    np.testing.assert_allclose(U, np.diag(np.exp(-0.5j * (Kzz @ th))), atol=1e-14)
+
+
+def test_k_rzz_columns_are_neighbour_parities():
+    """Column j of K_Rzz is +1 exactly where wires j and j+1 (mod n) hold the
+    same bit: checked on basis states written out bit by bit."""
+    n = 4
+    Kzz = sim.k_rzz_ring(n)
+    for idx in range(2 ** n):
+        bits = [(idx >> (n - 1 - w)) & 1 for w in range(n)]   # wire 0 = MSB
+        for j in range(n):
+            same = bits[j] == bits[(j + 1) % n]
+            assert Kzz[idx, j] == (1 if same else -1), (idx, j)
 
 
 @pytest.mark.parametrize("n", [1, 3, 5])
@@ -223,6 +242,45 @@ def test_o1_equals_o2_every_layer(spec, n):
     np.testing.assert_allclose(np.linalg.norm(o2, axis=1), 1.0, atol=1e-13)
     U = sim.layer_unitary(n, layers, 0, w, x[0])
     np.testing.assert_allclose(U.conj().T @ U, np.eye(2 ** n), atol=1e-13)
+
+
+WHOLE_CIRCUITS = [
+    ("rot_ring_zz", lambda n: W.circuit_rot_ring(n, 2, "RX", ("RX", "RY", "RZ"), zz=True), "normal"),
+    ("rot_ring", lambda n: W.circuit_rot_ring(n, 2, "RY", ("RY", "RZ")), "normal"),
+    ("ionq", lambda n: W.circuit_ionq(n, 2), "uniform2pi"),
+    ("ibm", lambda n: W.circuit_ibm(n, 2), "uniform2pi"),
+    ("ionq_qdi", lambda n: W.circuit_ionq(n, 2, "qdi"), "uniform2pi"),
+    ("ibm_qdi", lambda n: W.circuit_ibm(n, 2, "qdi"), "uniform2pi"),
+    ("rz_ry_cnot_qdi", lambda n: W.circuit_rz_ry_cnot(n, 2, "qdi"), "normal"),
+]
+
+
+@pytest.mark.parametrize("case", WHOLE_CIRCUITS, ids=[c[0] for c in WHOLE_CIRCUITS])
+@pytest.mark.parametrize("n", [2, 4, 6])
+def test_o1_equals_o2_whole_circuit(case, n):
+    """The O1 driver (per-sample products of full layer unitaries, Sec. 2.2.1)
+    against O2 (gate-by-gate contraction, Sec. 2.2.2) on whole circuits with
+    per-sample inputs, and the O1 readout path of forward_expval."""
+    _, build, dist = case
+    layers = build(n)
+    w, x = W.draw_params(n, layers, 3, dist, 31)
+    o1 = sim.run_o1(n, layers, w, x)
+    o2 = sim.run_o2(n, layers, w, x)
+    np.testing.assert_allclose(o1, o2, atol=1e-13)
+    np.testing.assert_allclose(sim.forward_expval(n, layers, w, x, tier="o1"),
+                               sim.forward_expval(n, layers, w, x, tier="o2"), atol=1e-13)
+
+
+def test_o1_layer_order_matters():
+    """Two non-commuting layers in either order give different O1 states, so
+    the O1 driver's layer order is observable (a reversed product would fail
+    the whole-circuit comparison above)."""
+    n = 2
+    a = [W.L("RY", "ALL", "INPUT"), W.L("CNOT", "RING"), W.L("RX", "ALL", "WEIGHT", offset=0)]
+    b = [a[0], a[2], a[1]]
+    w = np.array([0.4, -1.1])
+    x = np.array([[0.3, 1.2]])
+    assert np.abs(sim.run_o1(n, a, w, x) - sim.run_o1(n, b, w, x)).max() > 1e-2
 
 
 def test_embed_matrix_general_path_matches_kron():

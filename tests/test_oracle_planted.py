@@ -75,3 +75,54 @@ def test_wrong_ecr_row_is_caught(monkeypatch):
     bad[2, 1] = -bad[2, 1]
     monkeypatch.setitem(G.FIXED, "ECR", lambda: bad)
     _expect_failure(P.test_all_gates_unitary)
+
+
+def test_reversed_layer_order_in_o1_is_caught(monkeypatch):
+    def run_o1_reversed(n, layers, weights, features):
+        B = features.shape[0]
+        out = np.zeros((B, 2 ** n), dtype=np.complex128)
+        for b in range(B):
+            psi = np.zeros(2 ** n, dtype=np.complex128)
+            psi[0] = 1.0
+            for li in reversed(range(len(layers))):
+                psi = sim.layer_unitary(n, layers, li, weights, features[b]) @ psi
+            out[b] = psi
+        return out
+    monkeypatch.setattr(sim, "run_o1", run_o1_reversed)
+    _expect_failure(P.test_o1_equals_o2_whole_circuit, P.WHOLE_CIRCUITS[0], 4)
+
+
+def test_o1_without_per_sample_features_is_caught(monkeypatch):
+    def run_o1_first_row(n, layers, weights, features):
+        B = features.shape[0]
+        out = np.zeros((B, 2 ** n), dtype=np.complex128)
+        for b in range(B):
+            psi = np.zeros(2 ** n, dtype=np.complex128)
+            psi[0] = 1.0
+            for li in range(len(layers)):
+                psi = sim.layer_unitary(n, layers, li, weights, features[0]) @ psi
+            out[b] = psi
+        return out
+    monkeypatch.setattr(sim, "run_o1", run_o1_first_row)
+    _expect_failure(P.test_o1_equals_o2_whole_circuit, P.WHOLE_CIRCUITS[2], 4)
+
+
+def test_k_rzz_pairing_wrong_neighbour_is_caught(monkeypatch):
+    def k_rzz_left(n):
+        K = sim.k_rz(n)
+        return K * K[:, (np.arange(n) - 1) % n]
+    monkeypatch.setattr(sim, "k_rzz_ring", k_rzz_left)
+    _expect_failure(P.test_zz_ring_uses_k_rzz, 4)
+    _expect_failure(P.test_k_rzz_columns_are_neighbour_parities)
+
+
+def test_shared_parameter_shift_is_not_reported():
+    """A feature read by several layers has no two-term shift rule; the oracle
+    must leave it as NaN rather than return a one-gate value."""
+    import workloads as W
+    n = 3
+    layers = W.circuit_rz_ry_cnot(n, 2, "qdi")
+    w, x = W.draw_params(n, layers, 2, "normal", 3)
+    sw, sx = sim.grad_param_shift(n, layers, w, x, W.upstream(2, n, "normal", 1))
+    assert np.all(np.isnan(sx))
+    assert not np.any(np.isnan(sw))

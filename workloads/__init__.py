@@ -159,24 +159,50 @@ def circuit_rz_ry_cnot(n, blocks=8, encoding="qdi"):
     return b.layers
 
 
-def circuit_ionq(n, blocks=8):
-    """IonQ-style native gates: GPI2(0), RZ(x) encoding, then blocks of
-    [GPI, GPI2, MS on brick pairs] (Appendix B, Fig. 11(b))."""
-    b = _Builder(n).add("GPI2", "ALL", "FIXED", 0.0).add("RZ", "ALL", "INPUT")
+def _encoding_blocks(b, n, blocks, encoding, lead, block):
+    """Blocks of a native-gate circuit with its encoding pair [lead, RZ(x)].
+
+    "vq": the pair once, before the blocks (the features enter one layer).
+    "qdi": the pair opens every block, with the same n features (feature q on
+    wire q) re-uploaded each time, so the feature gradient sums over blocks."""
+    if encoding not in ("vq", "qdi"):
+        raise ValueError(encoding)
     for k in range(blocks):
+        if encoding == "qdi" or k == 0:
+            lead(b)
+            b.layers.append(L("RZ", "ALL", "INPUT", 0, 1, 0, 0.0))
+            b.nf = max(b.nf, n)
+        block(b, k)
+    if blocks == 0:
+        lead(b)
+        b.add("RZ", "ALL", "INPUT")
+    return b.layers
+
+
+def circuit_ionq(n, blocks=8, encoding="vq"):
+    """IonQ-style native gates (Appendix B, Fig. 11(b)): the encoding pair
+    GPI2(0), RZ(x), and blocks of [GPI, GPI2, MS on brick pairs]; the pair
+    sits before the blocks ("vq") or opens every block ("qdi")."""
+    def lead(b):
+        b.add("GPI2", "ALL", "FIXED", 0.0)
+
+    def block(b, k):
         b.add("GPI", "ALL", "WEIGHT").add("GPI2", "ALL", "WEIGHT")
         b.add("MS", "PAIRS_EVEN" if k % 2 == 0 else "PAIRS_ODD", "WEIGHT")
-    return b.layers
+    return _encoding_blocks(_Builder(n), n, blocks, encoding, lead, block)
 
 
-def circuit_ibm(n, blocks=8):
-    """IBM-style native gates: SX, RZ(x) encoding, then blocks of
-    [RZ, SX, RZ, ECR on brick pairs] (Appendix B, Fig. 11(a))."""
-    b = _Builder(n).add("SX", "ALL").add("RZ", "ALL", "INPUT")
-    for k in range(blocks):
+def circuit_ibm(n, blocks=8, encoding="vq"):
+    """IBM-style native gates (Appendix B, Fig. 11(a)): the encoding pair
+    SX, RZ(x), and blocks of [RZ, SX, RZ, ECR on brick pairs]; the pair sits
+    before the blocks ("vq") or opens every block ("qdi")."""
+    def lead(b):
+        b.add("SX", "ALL")
+
+    def block(b, k):
         b.add("RZ", "ALL", "WEIGHT").add("SX", "ALL").add("RZ", "ALL", "WEIGHT")
         b.add("ECR", "PAIRS_EVEN" if k % 2 == 0 else "PAIRS_ODD")
-    return b.layers
+    return _encoding_blocks(_Builder(n), n, blocks, encoding, lead, block)
 
 
 CONFIGS = {
