@@ -10,6 +10,7 @@ figures for the 20-qubit rotation + ZZ + CNOT-ring circuit (where the state
 set exceeds the on-chip caches), and the CPU oracle timed on a bounded sample.
 """
 import argparse
+import itertools
 import json
 import math
 import os
@@ -35,10 +36,17 @@ def parse():
     p.add_argument("--no-20q", action="store_true")
     p.add_argument("--mode", default="auto", choices=["auto", "per_layer", "fused"])
     p.add_argument("--no-serve", action="store_true")
-    p.add_argument("--serve-requests", type=int, default=160)
+    p.add_argument("--serve-requests", type=int, default=300,
+                   help="measured requests per arrival rate (2000 for the full protocol)")
     p.add_argument("--serve-max-qubits", type=int, default=22)
     p.add_argument("--serve-qps-fracs", default="0.5,0.8,0.95")
     p.add_argument("--no-b512", action="store_true")
+    p.add_argument("--no-extra", action="store_true",
+                   help="skip the complex128 headline, the 4-qubit and the 12-qubit legs")
+    p.add_argument("--serve-warmup", type=int, default=50,
+                   help="warm-up requests per arrival rate, left out of the statistics (200 for the full protocol)")
+    p.add_argument("--serve-only", action="store_true",
+                   help="run only the serving comparison and print its JSON")
     p.add_argument("--no-graph", action="store_true", help="time eager launches instead of a replayed HIP graph")
     # after the timed region, run a plain streaming kernel (float32 negation)
     # over this many MiB three times: the known-size reference that scales
@@ -92,7 +100,7 @@ def roofline(report, traffic_path=None):
 class Job:
     """One circuit at its full batch, device tensors resident in HBM."""
 
-    def __init__(self, name, mode, batch=None):
+    def __init__(self, name, mode, batch=None, dtype=None, grad=True):
         import torch
         import workloads as W
         from paper_2506_04891_amd import tqsim as T
@@ -101,8 +109,9 @@ class Job:
             cfg = W.CONFIGS[name]
             B = batch
             w, x = W.draw_params(n, layers, B, cfg["wdist"], cfg["seed"])
-        self.name, self.n, self.B = name, n, B
-        self.circ = T.Circuit(n, layers, dt, mode=mode)
+        self.name, self.n, self.B, self.grad = name, n, B, grad
+        self.layers, self.w_host, self.x_host = layers, w, x
+        self.circ = T.Circuit(n, layers, dtype or dt, mode=mode)
         dev = torch.device("cuda")
         self.w = torch.tensor(w, device=dev)
         self.x = torch.tensor(x, device=dev)
@@ -114,7 +123,11 @@ class Job:
         c = self.circ
         c.forward(self.w, self.x, state=self.state, ws=self.ws)
         self.e = c.expval_z(self.state, ws=self.ws)
-        self.gw, self.gx = c.adjoint_grad(self.w, self.x, self.state, self.g, ws=self.ws)
+        if self.grad:
+            self.gw, self.gx = c.adjoint_grad(self.w, self.x, self.state, self.g, ws=self.ws)
+
+    def outputs(self):
+        return (self.e, self.gw, self.gx) if self.grad else (self.e,)
 
 
 def time_jobs(jobs, steps, warmup):
@@ -126,18 +139,18 @@ def time_jobs(jobs, steps, warmup):
     for j in jobs:
         j.circ.profile_report(reset=True)
         j.circ.set_profile(True)
-    t0 = torch.cuda.Event(enable_timing=True)
-    t1 = torch.cuda.Event(enable_timing=True)
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(steps + 1)]
     torch.cuda.synchronize()
     wall0 = time.perf_counter()
-    t0.record()
-    for _ in range(steps):
+    ev[0].record()
+    for k in range(steps):
         for j in jobs:
             j.step()
-    t1.record()
+        ev[k + 1].record()
     torch.cuda.synchronize()
     wall = time.perf_counter() - wall0
-    ms = t0.elapsed_time(t1) / steps
+    per = [ev[k].elapsed_time(ev[k + 1]) for k in range(steps)]
+    ms = ev[0].elapsed_time(ev[steps]) / steps
     merged = {}
     for j in jobs:
         j.circ.set_profile(False)
@@ -145,20 +158,31 @@ def time_jobs(jobs, steps, warmup):
             m = merged.setdefault(k, {"count": 0, "ms": 0.0, "bytes": 0.0, "flops": 0.0})
             for f in m:
                 m[f] += v[f]
-    return ms, wall / steps * 1e3, merged
+    return ms, wall / steps * 1e3, merged, step_stats(per)
 
 
-def serving_bench(n_req, n_max, fracs, seed=0, streams=4, budget=160 << 30, heavy=256 << 20):
+def step_stats(per):
+    """mean, std and median of per-step times (ms): the paper's protocol
+    (mean and spread after warm-up, Sec. 2.1) and the median."""
+    import numpy as np
+    a = np.asarray(per, dtype=float)
+    return {"steps": int(a.size), "mean_ms": round(float(a.mean()), 4), "std_ms": round(float(a.std()), 4),
+            "median_ms": round(float(np.median(a)), 4), "min_ms": round(float(a.min()), 4),
+            "max_ms": round(float(a.max()), 4)}
+
+
+def serving_bench(n_req, n_max, fracs, seed=0, streams=4, budget=160 << 30, heavy=256 << 20, warm=200):
     """Continuous batching vs the plain per-request path on one Poisson trace of
     rotation + CNOT-ring circuits (qubits U{6..n_max}, batch log-U[1, 512],
-    blocks U{2..20}, 30% forward+gradient).  Launches reserving more than
-    `heavy` bytes fill the device alone and run one at a time."""
+    blocks U{2..20}, 30% forward+gradient): `warm` requests, then `n_req`
+    measured ones, per arrival rate.  Launches reserving more than `heavy`
+    bytes fill the device alone and run one at a time."""
     import numpy as np
     import workloads as W
     from paper_2506_04891_amd.serve import GpuExecutor, Request, Server
 
     def make(qps):
-        trace = W.serving_trace(n_req, qps=qps, seed=seed, n_range=(6, n_max))
+        trace = W.serving_trace(warm + n_req, qps=qps, seed=seed, n_range=(6, n_max))
         reqs = []
         for t in trace:
             layers, w, x = W.request_params(t, seed=seed)
@@ -176,7 +200,7 @@ def serving_bench(n_req, n_max, fracs, seed=0, streams=4, budget=160 << 30, heav
             futs.append(srv.submit(r))
         for f in futs:
             f.result(timeout=600)
-        st = srv.stats()
+        st = srv.stats(min_rid=warm)
         srv.close()
         return st
 
@@ -188,7 +212,7 @@ def serving_bench(n_req, n_max, fracs, seed=0, streams=4, budget=160 << 30, heav
     run([(0.0, Request(r.n, r.layers, r.weights, r.features, r.want_grad)) for _, r in base], True, ex_plain)
     sat = run([(0.0, r) for _, r in make(1e6)], False, ex)
     req_per_s = sat["requests"] / max(1e-9, (sat["evals"] / max(sat["evals_per_s"], 1e-9)))
-    out = {"trace": f"{n_req} requests, qubits U{{6..{n_max}}}, batch log-U[1,512], blocks U{{2..20}}, "
+    out = {"trace": f"{warm} warm-up + {n_req} measured requests per point, qubits U{{6..{n_max}}}, batch log-U[1,512], blocks U{{2..20}}, "
                     f"30% forward+gradient, seed {seed}; {streams} streams, one launch above "
                     f"{heavy >> 20} MiB at a time; warm circuits and graphs",
            "saturation": {"requests_per_s": round(req_per_s, 1), "evals_per_s": round(sat["evals_per_s"], 1)},
@@ -222,7 +246,7 @@ def time_graph(jobs, steps, warmup):
     with torch.cuda.graph(graph):
         for j in jobs:
             j.step()
-    outs = [(j.e, j.gw, j.gx) for j in jobs]
+    outs = [j.outputs() for j in jobs]
 
     def check(rounds):
         for _ in range(rounds):
@@ -233,7 +257,7 @@ def time_graph(jobs, steps, warmup):
                 j.step()
             torch.cuda.synchronize()
             for j, g in zip(jobs, got):
-                for a, b in zip(g, (j.e, j.gw, j.gx)):
+                for a, b in zip(g, j.outputs()):
                     if not torch.equal(a, b):
                         raise RuntimeError(f"graph replay of {j.name} differs from the eager step")
 
@@ -241,20 +265,20 @@ def time_graph(jobs, steps, warmup):
     for _ in range(warmup):
         graph.replay()
     torch.cuda.synchronize()
-    t0 = torch.cuda.Event(enable_timing=True)
-    t1 = torch.cuda.Event(enable_timing=True)
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(steps + 1)]
     torch.cuda.synchronize()
     wall0 = time.perf_counter()
-    t0.record()
-    for _ in range(steps):
+    ev[0].record()
+    for k in range(steps):
         graph.replay()
-    t1.record()
+        ev[k + 1].record()
     torch.cuda.synchronize()
     wall = time.perf_counter() - wall0
     check(1)
-    ms = t0.elapsed_time(t1) / steps
+    ms = ev[0].elapsed_time(ev[steps]) / steps
+    per = [ev[k].elapsed_time(ev[k + 1]) for k in range(steps)]
     del graph
-    return ms, wall / steps * 1e3
+    return ms, wall / steps * 1e3, step_stats(per)
 
 
 def dense_sweep(iters=30):
@@ -348,21 +372,25 @@ def dispatch_sweep(iters=10):
 
 
 def vq_qdi_sweep(iters=20):
-    """Fig. 8's measurement on the Rz-Ry-CNOT circuit of Fig. 6 (8 blocks):
-    forward (+ <Z_i>), backward (adjoint) and total time per call against the
-    number of qubits, at batch 1 and 64, for VQ and QDI encodings (c64)."""
+    """Fig. 8's measurement on the Rz-Ry-CNOT circuit of Fig. 6 (8 blocks), and
+    Figs. 12-13's on the IonQ and IBM native-gate circuits of App. B (8
+    blocks): forward (+ <Z_i>), backward (adjoint) and total time per call
+    against the number of qubits, at batch 1 and 64, for VQ and QDI encodings
+    (c64)."""
     import torch
     import workloads as W
     from paper_2506_04891_amd import tqsim as T
     dev = torch.device("cuda")
-    for enc in ("vq", "qdi"):
+    circuits = (("rz_ry_cnot", W.circuit_rz_ry_cnot, "normal"), ("ionq", W.circuit_ionq, "uniform2pi"),
+                ("ibm", W.circuit_ibm, "uniform2pi"))
+    for (cname, build, dist), enc in itertools.product(circuits, ("vq", "qdi")):
         for B in (1, 64):
             for n in (4, 6, 8, 10, 12, 14, 16, 18, 20, 22):
                 if B * (8 << n) > (4 << 30):
                     continue
-                layers = W.circuit_rz_ry_cnot(n, 8, enc)
+                layers = build(n, 8, enc)
                 c = T.Circuit(n, layers, "c64")
-                w, x = W.draw_params(n, layers, B, "normal", 0)
+                w, x = W.draw_params(n, layers, B, dist, 0)
                 wt, xt = torch.tensor(w, device=dev), torch.tensor(x, device=dev)
                 g = torch.ones((B, n), dtype=torch.float64, device=dev)
                 st = torch.empty((B, 2 ** n), dtype=c.complex_dtype, device=dev)
@@ -376,7 +404,8 @@ def vq_qdi_sweep(iters=20):
                     fwd()
                     c.adjoint_grad(wt, xt, st, g, ws=ws)
 
-                row = {"encoding": enc, "batch": B, "n": n, "passes": len(c.plan()["passes"])}
+                row = {"circuit": cname, "encoding": enc, "batch": B, "n": n,
+                       "passes": len(c.plan()["passes"])}
                 for name, fn in (("fwd", fwd), ("total", step)):
                     for _ in range(3):
                         fn()
@@ -429,82 +458,147 @@ def memory_sweep():
             del wt, xt, g, st, ws, e, gw, gx, c
 
 
-def _oracle_samples(samples, seed_offset=0, keep=None):
-    """Seconds the oracle (numpy complex128, one BLAS thread) takes for forward
-    <Z_i> + adjoint gradients of `samples` rows of each 16-qubit circuit.
-    keep: dict that receives {circuit: (rows, expz, grad_w, grad_x)}."""
-    import numpy as np
+C4 = ("c4a_16q_b128_ionq", "c4b_16q_b128_ibm")
+C3_ORACLE_ROWS = (0, 10, 21, 31)
+
+
+def _oracle_task(name, rows):
+    """<Z_i> and adjoint gradients of `rows` of a configuration in the oracle
+    (numpy complex128, one BLAS thread), upstream gradient one on those rows.
+    Returns (name, rows, expz, grad_w summed over the rows, grad_x, seconds)."""
     from threadpoolctl import threadpool_limits
     import workloads as W
     from oracle import sim
-    t = 0.0
+    n, B, dt, layers, w, x = W.config(name)
+    rows = list(rows)
     with threadpool_limits(limits=1):
-        for name in ("c4a_16q_b128_ionq", "c4b_16q_b128_ibm"):
-            n, B, dt, layers, w, x = W.config(name)
-            rows = [(seed_offset + k) % B for k in range(samples)]
-            xs = x[rows]
-            g = W.upstream(samples, n, "ones")
-            t0 = time.perf_counter()
-            res = sim.grad_adjoint(n, layers, w, xs, g)
-            t += time.perf_counter() - t0
-            if keep is not None:
-                keep[name] = (rows, *res)
-    return t
+        t0 = time.perf_counter()
+        e, gw, gx = sim.grad_adjoint(n, layers, w, x[rows], W.upstream(len(rows), n, "ones"))
+        return name, rows, e, gw, gx, time.perf_counter() - t0
 
 
-def _pool_worker(k, per_worker):
-    return _oracle_samples(per_worker, seed_offset=k * per_worker)
+def _merge(results):
+    """Concatenate per-task oracle results per configuration (weight
+    gradients summed over the tasks' rows)."""
+    import numpy as np
+    out = {}
+    for name, rows, e, gw, gx, t in results:
+        if name not in out:
+            out[name] = [list(rows), [e], gw.copy(), [gx], t]
+        else:
+            o = out[name]
+            o[0] += rows
+            o[1].append(e)
+            o[2] += gw
+            o[3].append(gx)
+            o[4] += t
+    return {k: (v[0], np.concatenate(v[1]), v[2], np.concatenate(v[3]), v[4]) for k, v in out.items()}
 
 
-def cpu_baseline(sample=12, keep=None):
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(sample=12):
     """The oracle on `sample` rows of each 16-qubit circuit, one thread."""
-    t = _oracle_samples(sample, keep=keep)
+    t = sum(_oracle_task(name, range(sample))[-1] for name in C4)
     evals = 2 * sample
     return {"value": round(evals / t, 3), "unit": "circuit evals/s", "cores": 1, "kind": "oracle",
             "sample": f"{sample} rows of each 16-qubit circuit (IonQ and IBM gate sets), forward + adjoint "
                       f"gradients in numpy complex128 on one thread (BLAS limited to 1); {round(t, 2)} s; "
-                      f"host has {os.cpu_count()} logical CPUs"}
+                      f"host: {cpu_model()}, {os.cpu_count()} logical CPUs"}
 
 
-def errors_vs_oracle(jobs, ref):
-    """Max errors of the benchmarked GPU path against the oracle rows kept by
-    cpu_baseline: <Z_i> (max abs), weight and feature gradients (max abs over
-    max |ref|), with the upstream gradient one on those rows and zero elsewhere."""
+def oracle_pool():
+    """The oracle over a process pool (one process per core, one thread each,
+    at most 16), parallel over samples.  First every row of both 16-qubit
+    circuits (timed: the all-cores baseline); then four rows of the 20-qubit
+    circuit, every row of the 12-qubit one and the 4-qubit forward.  The
+    results are kept to check the GPU outputs on the same rows.  Run before
+    the GPU is initialised: the pool forks this process."""
+    import multiprocessing as mp
+    cores = max(1, min(16, os.cpu_count() or 1))
+    with mp.get_context("fork").Pool(cores) as pool:
+        t0 = time.perf_counter()
+        r16 = pool.starmap(_oracle_task, [(name, range(k, k + 8)) for name in C4 for k in range(0, 128, 8)])
+        wall16 = time.perf_counter() - t0
+        t1 = time.perf_counter()
+        other = ([("c3_20q_b32", [r]) for r in C3_ORACLE_ROWS] +
+                 [("c2_12q_b256", range(k, k + 32)) for k in range(0, 256, 32)] + [("c1_4q_b16", range(16))])
+        rest = pool.starmap(_oracle_task, other)
+        wall_rest = time.perf_counter() - t1
+    ref = _merge(r16 + rest)
+    c3_t = [r[-1] for r in rest if r[0] == "c3_20q_b32"]
+    return ref, {
+        "all_cores": {"value": round(256 / wall16, 3), "unit": "circuit evals/s", "cores": cores, "kind": "oracle",
+                      "sample": f"all 128 rows of each 16-qubit circuit over {cores} processes (one thread each); "
+                                f"{round(wall16, 2)} s wall including pool start-up"},
+        "c3_20q_b32": {"rows": list(C3_ORACLE_ROWS), "seconds_per_eval": round(sum(c3_t) / len(c3_t), 2),
+                       "evals_per_s_one_core": round(len(c3_t) / sum(c3_t), 4),
+                       "sample": "4 of the 32 samples, forward + adjoint, one process per row, one thread each"},
+        "c2_12q_b256": {"evals_per_s_one_core": round(256 / ref["c2_12q_b256"][4], 2),
+                        "sample": "all 256 rows, forward + adjoint"},
+        "c1_4q_b16": {"cpu_seconds": round(ref["c1_4q_b16"][4], 4),
+                      "sample": "all 16 rows, forward <Z_i> (and the adjoint, which the oracle computes with it)"},
+        "wall_s_other": round(wall_rest, 2)}
+
+
+def errors_vs_oracle(job, ref):
+    """Max errors of the GPU path against the oracle rows `ref`: <Z_i> (max
+    abs), weight and feature gradients (max abs over max |ref|), with the
+    upstream gradient one on those rows and zero elsewhere."""
     import numpy as np
     import torch
-    out = {}
-    for j in jobs:
-        if j.name not in ref:
-            continue
-        rows, e_ref, gw_ref, gx_ref = ref[j.name]
-        c = j.circ
-        c.forward(j.w, j.x, state=j.state, ws=j.ws)
-        e = c.expval_z(j.state, ws=j.ws).cpu().numpy()
-        g = torch.zeros_like(j.g)
+    rows, e_ref, gw_ref, gx_ref, _ = ref
+    c = job.circ
+    c.forward(job.w, job.x, state=job.state, ws=job.ws)
+    e = c.expval_z(job.state, ws=job.ws).cpu().numpy()
+    out = {"rows": rows if len(rows) <= 16 else f"all {len(rows)}",
+           "expz_max_abs": float(np.max(np.abs(e[rows] - e_ref)))}
+    if job.grad:
+        g = torch.zeros_like(job.g)
         g[rows] = 1.0
-        gw, gx = c.adjoint_grad(j.w, j.x, j.state, g, ws=j.ws)
+        gw, gx = c.adjoint_grad(job.w, job.x, job.state, g, ws=job.ws)
         gw, gx = gw.cpu().numpy(), gx.cpu().numpy()
-        out[j.name] = {"rows": rows,
-                       "expz_max_abs": float(np.max(np.abs(e[rows] - e_ref))),
-                       "grad_weights_max_rel": float(np.max(np.abs(gw - gw_ref)) / np.max(np.abs(gw_ref))),
-                       "grad_features_max_rel": float(np.max(np.abs(gx[rows] - gx_ref)) / np.max(np.abs(gx_ref)))}
+        out["grad_weights_max_rel"] = float(np.max(np.abs(gw - gw_ref)) / np.max(np.abs(gw_ref)))
+        out["grad_features_max_rel"] = float(np.max(np.abs(gx[rows] - gx_ref)) / np.max(np.abs(gx_ref)))
     return out
 
 
-def cpu_baseline_pool(per_worker=6):
-    """The same oracle over a process pool (one process per core, one thread
-    each; at most 16 cores), parallel over samples.  Run before the GPU is
-    initialised: the pool forks this process."""
-    import multiprocessing as mp
-    cores = max(1, min(16, os.cpu_count() or 1))
-    t0 = time.perf_counter()
-    with mp.get_context("fork").Pool(cores) as pool:
-        pool.starmap(_pool_worker, [(k, per_worker) for k in range(cores)])
-    wall = time.perf_counter() - t0
-    evals = 2 * per_worker * cores
-    return {"value": round(evals / wall, 3), "unit": "circuit evals/s", "cores": cores, "kind": "oracle",
-            "sample": f"{per_worker} rows of each 16-qubit circuit per process, {cores} processes; "
-                      f"{round(wall, 2)} s wall including pool start-up"}
+def pass_bandwidth(rep):
+    """HBM bytes over time of the tile-pass launches (algorithmic bytes: one
+    read and one write of each state a pass streams), forward, backward and
+    both, against the 8 TB/s peak."""
+    out = {}
+    for label, pre in (("fwd", "pass_fwd"), ("bwd", "pass_bwd"), ("all", "pass_")):
+        ks = [v for k, v in rep.items() if k.startswith(pre)]
+        ms = sum(v["ms"] for v in ks)
+        by = sum(v["bytes"] for v in ks)
+        if ms > 0:
+            out[label] = {"GBps": round(by / (ms / 1e3) / 1e9, 1), "frac": round(by / (ms / 1e3) / 1e9 / HBM_PEAK_GBS, 4),
+                          "launches": sum(v["count"] for v in ks), "ms": round(ms, 3)}
+    return out
+
+
+# The paper's own figures (context, not targets: other hardware, its own
+# PyTorch implementation in complex128, against PennyLane default.qubit).
+PAPER_CONTEXT = [
+    {"claim": "forward + backward speedup over PennyLane default.qubit", "value": "about 10x for n <= 10, "
+     "about 3x beyond", "hardware": "1 CPU thread and 1 GPU (model not named)", "where": "Sec. 3, Fig. 8"},
+    {"claim": "IBM native-gate QDI circuit speedup", "value": "up to about 10x up to about 15 qubits, then "
+     "converging", "hardware": "1 CPU thread, 1 GPU", "where": "App. B, Fig. 12"},
+    {"claim": "IonQ native-gate QDI circuit speedup", "value": "about 10x; 20 qubits reached vs 17 at batch 1",
+     "hardware": "1 CPU thread, 1 GPU", "where": "App. B, Fig. 13"},
+    {"claim": "PyTorch steady-state speedup over PennyLane-Torch", "value": "up to 10x", "hardware":
+     "48-core CPU node; 1 NVIDIA A100", "where": "Sec. 4"},
+]
 
 
 def main():
@@ -514,10 +608,9 @@ def main():
         sys.exit(2)
     # the CPU baselines run first: the pooled one forks, which must happen
     # before anything initialises the GPU in this process
-    oracle_rows = {}
-    sweep = a.dense_sweep or a.dispatch_sweep or a.vq_qdi_sweep or a.memory_sweep
-    cpu = None if (a.no_cpu_baseline or sweep) else cpu_baseline(keep=oracle_rows)
-    cpu_pool = None if (a.no_cpu_baseline or sweep) else cpu_baseline_pool()
+    sweep = a.dense_sweep or a.dispatch_sweep or a.vq_qdi_sweep or a.memory_sweep or a.serve_only
+    cpu = None if (a.no_cpu_baseline or sweep) else cpu_baseline()
+    ref, cpu_pool = ({}, None) if (a.no_cpu_baseline or sweep) else oracle_pool()
     import torch
     if not torch.cuda.is_available():
         print(json.dumps({"error": "no GPU visible"}))
@@ -536,14 +629,21 @@ def main():
     if a.memory_sweep:
         memory_sweep()
         return
+    if a.serve_only:
+        print(json.dumps(serving_bench(a.serve_requests, a.serve_max_qubits,
+                                       [float(f) for f in a.serve_qps_fracs.split(",")], warm=a.serve_warmup)))
+        return
 
-    jobs = [Job("c4a_16q_b128_ionq", a.mode), Job("c4b_16q_b128_ibm", a.mode)]
+    def errs(j):
+        return errors_vs_oracle(j, ref[j.name]) if j.name in ref else None
+
+    jobs = [Job(name, a.mode) for name in C4]
     # per-kernel times: an eager run with the library's HIP events
-    ms_eager, wall_eager, rep = time_jobs(jobs, a.steps, a.warmup)
+    ms_eager, wall_eager, rep, st_eager = time_jobs(jobs, a.steps, a.warmup)
     if a.no_graph:
-        ms, wall_ms = ms_eager, wall_eager
+        ms, wall_ms, st = ms_eager, wall_eager, st_eager
     else:
-        ms, wall_ms = time_graph(jobs, a.steps, a.warmup)
+        ms, wall_ms, st = time_graph(jobs, a.steps, a.warmup)
     evals = sum(j.B for j in jobs)
     value = evals / (ms / 1e3)
     out = {
@@ -554,6 +654,8 @@ def main():
         "steps": a.steps,
         "warmup": a.warmup,
         "ms_per_step": round(ms, 4),
+        "step_stats": st,
+        "evals_per_s_at_median": round(evals / (st["median_ms"] / 1e3), 1),
         "wall_ms_per_step": round(wall_ms, 4),
         "execution": ("eager launches" if a.no_graph else
                       "one HIP graph per step (both circuits' forward, <Z_i> and adjoint), replayed; "
@@ -562,7 +664,9 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "c64 (f32 state, f64 reductions)",
+        "dtype": "c64",
+        "precision": "complex64 states; FP64 gate matrices and angles; every sum over amplitudes beyond one "
+                     "thread's 16 registers (gradient partials, <Z_i>, norms) in FP64",
         "data": "synthetic (seeded weights U(0,2pi), features U(-pi,pi), upstream dL/d<Z>=1)",
         "config": {"workload": "16 qubits, batch 128, complex64: IonQ GPI/GPI2/MS and IBM RZ/SX/ECR "
                                "native-gate circuits, 8 blocks each, forward <Z_i> + adjoint gradients",
@@ -570,8 +674,9 @@ def main():
                    "mode": a.mode, "passes": {j.name: len(j.circ.plan()["passes"]) for j in jobs}},
         "roofline": roofline(rep, traffic_file),
         "kernels": {k: {"count": v["count"], "ms_per_step": round(v["ms"] / a.steps, 4)} for k, v in rep.items()},
-        "errors_vs_oracle": errors_vs_oracle(jobs, oracle_rows),
+        "errors_vs_oracle": {j.name: errs(j) for j in jobs},
     }
+    del jobs
     if a.calibrate_copy_mib > 0:
         src = torch.ones(a.calibrate_copy_mib << 18, dtype=torch.float32, device="cuda")
         dst = torch.empty_like(src)
@@ -579,28 +684,63 @@ def main():
             torch.neg(src, out=dst)
         torch.cuda.synchronize()
         del src, dst
+    short = max(5, a.steps // 2)
+    if not a.no_extra:
+        # the headline workload in complex128 (the paper's precision, Sec. 2.1)
+        j128 = [Job(name, a.mode, dtype="c128") for name in C4]
+        ms128, _, st128 = time_graph(j128, short, 2)
+        out["q16_c128"] = {"workload": "the headline workload in complex128", "evals_per_s": round(256 / (ms128 / 1e3), 1),
+                           "ms_per_step": round(ms128, 4), "step_stats": st128,
+                           "errors_vs_oracle": {j.name: errs(j) for j in j128}}
+        del j128
+        # 4 qubits, batch 16, complex128, plain forward <Z_i>
+        j1 = Job("c1_4q_b16", a.mode, grad=False)
+        ms1, _, st1 = time_graph([j1], a.steps, a.warmup)
+        out["c1_4q_b16"] = {"workload": "4 qubits, batch 16, complex128: RY(x) + 2 x [RX, RZ, CNOT ring], forward <Z_i>",
+                            "ms_per_step": round(ms1, 4), "step_stats": st1,
+                            "evals_per_s": round(16 / (ms1 / 1e3), 1), "errors_vs_oracle": errs(j1)}
+        del j1
+        # 12 qubits, batch 256, complex64, forward + adjoint
+        j2 = Job("c2_12q_b256", a.mode)
+        ms2, _, st2 = time_graph([j2], a.steps, a.warmup)
+        out["c2_12q_b256"] = {"workload": "12 qubits, batch 256, complex64: RY(x) + 10 x [RY, RZ, CNOT ring], "
+                                          "forward <Z_i> + adjoint gradients",
+                              "ms_per_step": round(ms2, 4), "step_stats": st2,
+                              "evals_per_s": round(256 / (ms2 / 1e3), 1), "errors_vs_oracle": errs(j2)}
+        del j2
     if not a.no_b512:
-        jb = [Job("c4a_16q_b128_ionq", a.mode, 512), Job("c4b_16q_b128_ibm", a.mode, 512)]
-        msb, _, repb = time_jobs(jb, max(3, a.steps // 4), 2)
+        jb = [Job(name, a.mode, 512) for name in C4]
+        msb, _, repb, stb = time_jobs(jb, max(3, a.steps // 4), 2)
         out["q16_b512"] = {"workload": "the same two 16-qubit circuits at batch 512 (256 MiB per state set, "
                                        "larger than the last-level cache)",
                            "evals_per_s": round(1024 / (msb / 1e3), 1), "ms_per_step": round(msb, 3),
-                           "roofline": roofline(repb)}
+                           "step_stats": stb, "roofline": roofline(repb),
+                           "pass_bandwidth": pass_bandwidth(repb)}
         del jb
     if not a.no_20q:
         j20 = Job("c3_20q_b32", a.mode)
-        ms20, _, rep20 = time_jobs([j20], max(3, a.steps // 4), 2)
+        ms20e, _, rep20, st20e = time_jobs([j20], max(5, a.steps // 2), 2)
+        ms20, _, st20 = time_graph([j20], max(5, a.steps // 2), 2)
         out["q20"] = {"workload": "20 qubits, batch 32, complex64: RX embedding + 6 x [RX, RY, RZ, ZZ ring, "
                                   "CNOT ring], forward <Z_i> + adjoint gradients",
                       "evals_per_s": round(j20.B / (ms20 / 1e3), 1), "ms_per_step": round(ms20, 3),
+                      "step_stats": st20, "eager_ms_per_step": round(ms20e, 3),
+                      "hbm": pass_bandwidth(rep20),
                       "roofline": roofline(rep20, lambda k: traffic_file(k, "20q_b32")),
-                      "kernels": {k: {"count": v["count"], "ms": round(v["ms"], 3)} for k, v in rep20.items()}}
+                      "kernels": {k: {"count": v["count"], "ms": round(v["ms"], 3)} for k, v in rep20.items()},
+                      "errors_vs_oracle": errs(j20)}
         del j20
     if not a.no_serve:
         out["serving"] = serving_bench(a.serve_requests, a.serve_max_qubits,
-                                       [float(f) for f in a.serve_qps_fracs.split(",")])
+                                       [float(f) for f in a.serve_qps_fracs.split(",")],
+                                       warm=a.serve_warmup)
     out["cpu_baseline"] = cpu
-    out["cpu_baseline_all_cores"] = cpu_pool
+    if cpu_pool is not None:
+        out["cpu_baseline_all_cores"] = cpu_pool.pop("all_cores")
+        out["cpu_oracle_other"] = cpu_pool
+    out["host"] = {"cpu_model": cpu_model(), "logical_cpus": os.cpu_count(),
+                   "gpu": torch.cuda.get_device_name(0)}
+    out["paper_context"] = PAPER_CONTEXT
     print(json.dumps(out))
 
 

@@ -45,16 +45,18 @@ def build(verbose=False, if_changed=False):
     os.makedirs(BUILD, exist_ok=True)
     planner_o = os.path.join(BUILD, "planner.o")
     inc = ["-I", CSRC, "-I", INCLUDE]
-    common = [os.path.join(CSRC, f) for f in ("kernels.hip", "plan.h", "planner.h", "pass_launch.h",
-                                               "pass_tu.inc")]
-    common.append(os.path.join(INCLUDE, "tqsim.h"))
+    # files each unit includes: the pass units see the kernels and the plan
+    # layout only; the host API unit also the planner and the public header
+    pass_deps = [os.path.join(CSRC, f) for f in ("kernels.hip", "plan.h", "pass_launch.h", "pass_tu.inc")]
+    host_deps = pass_deps + [os.path.join(CSRC, "planner.h"), os.path.join(INCLUDE, "tqsim.h")]
     units = ["tqsim", *PASS_UNITS]
     procs, objs = [], []
     for u in units:
         src = os.path.join(CSRC, u + ".hip")
         obj = os.path.join(BUILD, u + ".o")
         objs.append(obj)
-        if if_changed and not _stale(obj, [src, *common]):
+        deps = host_deps if u == "tqsim" else pass_deps
+        if if_changed and not _stale(obj, [src, *deps]):
             continue
         cmd = ["hipcc", *HIP_FLAGS, *inc, "-c", src, "-o", obj]
         procs.append((cmd, subprocess.Popen(cmd, stdout=subprocess.PIPE, stderr=subprocess.STDOUT, text=True)))

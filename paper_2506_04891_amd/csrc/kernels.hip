@@ -679,11 +679,12 @@ struct PassArgs {
   kptr<double> dbl;
   kptr<double> dbl_ps;
   int dbl_ps_stride;
+  const cplx<T> *diag_tabs;   // prebuilt split tables of shared diagonal ops
   const cplx<T> *src0;
   cplx<T> *dst0;
   const cplx<T> *src1;
   cplx<T> *dst1;
-  T *partials;
+  double *partials;       // FP64 gradient partials of every pass
   long long acc_region;   // first partial of this pass
   int units;              // partial units per sample of this pass
   int batch;
@@ -804,18 +805,18 @@ struct Ctx {
   int units_wg_base;    // unit offset of this workgroup within its sample (single mode)
   // gradient partials (backward): the thread's slot for accumulator 0, the
   // distance between accumulators, and whether the thread writes its segment's sum
-  T *pslot;
+  double *pslot;
   long long pstride;
   int pwriter;
   // whole-wave segments: lanes 0-2 write the three sums of a transposed reduction
-  T *pslot3;
+  double *pslot3;
   int pwriter3;
 };
 
 // Partial slot of the thread: partials[acc_region + (acc * batch + s) * units + u]
 // for the sample s and unit u of the thread's reduction segment.
 template <typename T, int K>
-__device__ __forceinline__ void set_partial_slot(Ctx<T, K> &c, T *partials, long long acc_region, int batch,
+__device__ __forceinline__ void set_partial_slot(Ctx<T, K> &c, double *partials, long long acc_region, int batch,
                                                  int units) {
   const int segm = (1 << c.seg_log) - 1;
   const int seg = c.tid >> c.seg_log;
@@ -844,28 +845,33 @@ __device__ __forceinline__ int thread_sample(const Ctx<T, K> &c, int batch) {
 }
 
 // Three sums of consecutive accumulators acc, acc+1, acc+2 (the Pauli sums of
-// one single-qubit gradient), reduced together.
+// one single-qubit gradient), reduced together.  Each thread's sums over its
+// own amplitudes arrive in the state's precision; they are widened to FP64
+// before the cross-lane tree, so every sum over amplitudes beyond one thread's
+// registers is FP64, and the partials are stored as FP64.
 template <typename T, int K>
 __device__ __forceinline__ void write_acc3(const Ctx<T, K> &c, const PassArgs<T> &a, T x, T y, T z, int acc) {
+  double xd = (double)x, yd = (double)y, zd_ = (double)z;
   if (__builtin_amdgcn_readfirstlane(c.seg_log) == 6) {
-    const T v = wave_sum3_transposed(x, y, z, c.lane);
+    const double v = wave_sum3_transposed(xd, yd, zd_, c.lane);
     if (c.pwriter3) c.pslot3[(long long)acc * c.pstride] = v;
     return;
   } else {
-    x = seg_sum_dpp(x, c.seg_log);
-    y = seg_sum_dpp(y, c.seg_log);
-    z = seg_sum_dpp(z, c.seg_log);
+    xd = seg_sum_dpp(xd, c.seg_log);
+    yd = seg_sum_dpp(yd, c.seg_log);
+    zd_ = seg_sum_dpp(zd_, c.seg_log);
   }
   if (c.pwriter) {
-    T *p = c.pslot + (long long)acc * c.pstride;
-    p[0] = x;
-    p[c.pstride] = y;
-    p[2 * c.pstride] = z;
+    double *p = c.pslot + (long long)acc * c.pstride;
+    p[0] = xd;
+    p[c.pstride] = yd;
+    p[2 * c.pstride] = zd_;
   }
 }
 
+// One sum (a thread's share, any precision) reduced over its segment in FP64.
 template <typename T, int K>
-__device__ __forceinline__ void write_acc(const Ctx<T, K> &c, const PassArgs<T> &a, T v, int acc) {
+__device__ __forceinline__ void write_acc(const Ctx<T, K> &c, const PassArgs<T> &a, double v, int acc) {
   // one uniform test: whole-wave segments (every single-sample tile) take the
   // straight-line reduction
   if (__builtin_amdgcn_readfirstlane(c.seg_log) == 6)
@@ -1176,52 +1182,103 @@ __device__ __forceinline__ T wht_pick(const T (&w)[NREG], int m) {
   }
 }
 
-// Build the split phase tables of every diagonal op of the pass in LDS.
+// Phase angle of entry `idx` of a diagonal op's split tables (the TL entries
+// first, then TH) for the tile whose bits outside the tile are `base`, and
+// sample `smp` for terms with per-sample angles: the sum of the term angles
+// (FP64) selected by the entry's bits.
+__device__ __forceinline__ double diag_entry_angle(kptr<DevDiag> dg, kptr<DevTerm> terms, kptr<double> dbl,
+                                                   kptr<double> dbl_ps, int dbl_ps_stride, uint32_t base,
+                                                   int smp, int idx) {
+  const int h = uni(dg->h), nx = uni(dg->n_extra);
+  const int tbeg = uni(dg->term_begin), tend = uni(dg->term_end);
+  const int ex0 = nx > 0 ? uni(dg->extra[0]) : -1, ex1 = nx > 1 ? uni(dg->extra[1]) : -1;
+  const int nl = 1 << (h + nx);
+  const bool low = idx < nl;
+  const int e = low ? idx : idx - nl;
+  double ang = 0.0;
+  for (int ti = tbeg; ti < tend; ++ti) {
+    kptr<DevTerm> tm = terms + ti;
+    const int tab_id = uni(tm->tab);
+    if (low ? (tab_id != 0) : (tab_id == 0)) continue;
+    const int nb = uni(tm->nbits);
+    int v = 0;
+    for (int q = 0; q < nb; ++q) {
+      int bit;
+      const int tb = uni(tm->tb[q]);
+      if (tb < 0) {
+        bit = (base >> uni(tm->gb[q])) & 1;
+      } else if (low) {
+        if (tb < h)
+          bit = (e >> tb) & 1;
+        else
+          bit = (e >> (h + (tb == ex0 ? 0 : (tb == ex1 ? 1 : 2)))) & 1;
+      } else {
+        bit = (e >> (tb - h)) & 1;
+      }
+      v = (v << 1) | bit;
+    }
+    const int ang_off = uni(tm->ang);
+    kptr<double> an = uni(tm->per_sample) ? dbl_ps + (size_t)smp * dbl_ps_stride + ang_off : dbl + ang_off;
+    ang += an[v];
+  }
+  return ang;
+}
+
+// The split phase tables of every diagonal op of the pass, in LDS: copied from
+// the prebuilt tables of tile position `tile` for ops with shared angles,
+// built here for ops with per-sample angles.
 template <typename T, int K>
-__device__ __forceinline__ void build_diag_tables(const Ctx<T, K> &c, const PassArgs<T> &a, cplx<T> *tab) {
+__device__ __forceinline__ void build_diag_tables(const Ctx<T, K> &c, const PassArgs<T> &a, cplx<T> *tab,
+                                                  int tile) {
   kptr<DevPass> P = a.pass;
   const int nd = uni(P->n_diag), db = uni(P->diag_begin);
   for (int di = 0; di < nd; ++di) {
     kptr<DevDiag> dg = a.diags + db + di;
-    const int h = uni(dg->h), nx = uni(dg->n_extra), off = uni(dg->lds_off);
-    const int tbeg = uni(dg->term_begin), tend = uni(dg->term_end);
-    const int ex0 = nx > 0 ? uni(dg->extra[0]) : -1, ex1 = nx > 1 ? uni(dg->extra[1]) : -1;
-    const int nl = 1 << (h + nx), nh = 1 << (K - h);
-    for (int idx = c.tid; idx < nl + nh; idx += Ctx<T, K>::NT) {
-      const bool low = idx < nl;
-      const int e = low ? idx : idx - nl;
-      double ang = 0.0;
-      for (int ti = tbeg; ti < tend; ++ti) {
-        kptr<DevTerm> tm = a.terms + ti;
-        const int tab_id = uni(tm->tab);
-        if (low ? (tab_id != 0) : (tab_id == 0)) continue;
-        const int nb = uni(tm->nbits);
-        int v = 0;
-        for (int q = 0; q < nb; ++q) {
-          int bit;
-          const int tb = uni(tm->tb[q]);
-          if (tb < 0) {
-            bit = (c.base >> uni(tm->gb[q])) & 1;
-          } else if (low) {
-            if (tb < h)
-              bit = (e >> tb) & 1;
-            else
-              bit = (e >> (h + (tb == ex0 ? 0 : (tb == ex1 ? 1 : 2)))) & 1;
-          } else {
-            bit = (e >> (tb - h)) & 1;
-          }
-          v = (v << 1) | bit;
-        }
-        const int ang_off = uni(tm->ang);
-        kptr<double> an = uni(tm->per_sample) ? a.dbl_ps + (size_t)c.sample0 * a.dbl_ps_stride + ang_off
-                                              : a.dbl + ang_off;
-        ang += an[v];
-      }
+    const int h = uni(dg->h), nx = uni(dg->n_extra), off = uni(dg->lds_off), gt = uni(dg->gtab);
+    const int n_ent = (1 << (h + nx)) + (1 << (K - h));
+    if (gt >= 0) {
+      const cplx<T> *src = a.diag_tabs + gt + (long long)tile * n_ent;
+      for (int idx = c.tid; idx < n_ent; idx += Ctx<T, K>::NT) tab[off + idx] = src[idx];
+      continue;
+    }
+    for (int idx = c.tid; idx < n_ent; idx += Ctx<T, K>::NT) {
+      const double ang = diag_entry_angle(dg, a.terms, a.dbl, a.dbl_ps, a.dbl_ps_stride, c.base, c.sample0, idx);
       double s, co;
       sincos(ang, &s, &co);
       tab[off + idx] = cmk<T>((T)co, (T)s);
     }
   }
+}
+
+// Prebuilt split tables of the diagonal ops with shared angles, for every tile
+// position of their pass (one thread per entry).  Run after k_prep, which
+// writes the angles.
+template <typename T>
+struct DiagTabArgs {
+  kptr<DevPass> passes;
+  kptr<DevDiag> diags;
+  kptr<DevTerm> terms;
+  kptr<DiagJob> jobs;
+  kptr<double> dbl;
+  cplx<T> *out;
+};
+
+template <typename T>
+__global__ void __launch_bounds__(256) k_diag_tables(DiagTabArgs<T> a) {
+  kptr<DiagJob> j = a.jobs + blockIdx.y;
+  const int entries = uni(j->entries), tiles_log = uni(j->tiles_log);
+  const long long i = (long long)blockIdx.x * 256 + threadIdx.x;
+  if (i >= ((long long)entries << tiles_log)) return;
+  const int tile = (int)(i / entries), idx = (int)(i % entries);
+  kptr<DevPass> P = a.passes + uni(j->pass);
+  uint32_t base = 0;
+  for (int r = 0; r < tiles_log; ++r)
+    if ((tile >> r) & 1) base |= 1u << uni(P->rest[r]);
+  kptr<DevDiag> dg = a.diags + uni(j->diag);
+  const double ang = diag_entry_angle(dg, a.terms, a.dbl, a.dbl, 0, base, 0, idx);
+  double s, co;
+  sincos(ang, &s, &co);
+  a.out[uni(dg->gtab) + i] = cmk<T>((T)co, (T)s);
 }
 
 // Split-table phase of tile element t.  The extra index bits are passed in
@@ -1601,7 +1658,7 @@ __device__ __forceinline__ void outside_embed_grads(const Ctx<T, K> &c, const Pa
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
       const double dr = cr[k] * rx - ci[k] * ry, di = cr[k] * ry + ci[k] * rx;
-      write_acc(c, a, (T)(dr * sy + di * sx), acc + k);     // Im(D * S)
+      write_acc(c, a, dr * sy + di * sx, acc + k);     // Im(D * S)
     }
     acc += 3;
   }
@@ -1658,7 +1715,8 @@ __attribute__((amdgpu_waves_per_eu(PassOcc<T, BWD, DENSE>::waves))) k_pass(PassA
   c.pwriter = 0;
   if (BWD) set_partial_slot(c, a.partials, a.acc_region, a.batch, a.units);
 
-  if (DIAG && uni(P->n_diag) > 0) build_diag_tables<T, K>(c, a, tab);
+  if (DIAG && uni(P->n_diag) > 0)
+    build_diag_tables<T, K>(c, a, tab, c.multi ? 0 : (int)((uint32_t)wg & ((1u << (c.nv - K)) - 1u)));
 
   // ---------------- load ----------------
   // Element e = tid + i * NT has tile index e; tile bits 0..K-RB-1 come from
@@ -2147,8 +2205,8 @@ __global__ void __launch_bounds__(NTE) k_adj_init(ReadArgs<T> a) {
 // host from the longest sum), each lane summing a fixed stride of the terms in
 // order, then a fixed DPP tree within the group.  Blocks of NTR threads.
 
-template <typename T>
-__global__ void __launch_bounds__(NTR) k_acc_reduce(const T *partials, const long long *acc_static,
+#ifndef TQS_PASS_TU   // defined once, in the translation unit of the host API
+__global__ void __launch_bounds__(NTR) k_acc_reduce(const double *partials, const long long *acc_static,
                                                     const int *acc_units, int n_acc, int batch, double *A,
                                                     int gl) {
   const long long o = ((long long)blockIdx.x * NTR + threadIdx.x) >> gl;
@@ -2158,12 +2216,13 @@ __global__ void __launch_bounds__(NTR) k_acc_reduce(const T *partials, const lon
   if (valid) {
     const int acc = (int)(o / batch), b = (int)(o % batch);
     const int U = acc_units[acc];
-    const T *p = partials + acc_static[acc] * batch + (long long)b * U;
-    for (int u = g; u < U; u += (1 << gl)) s += (double)p[u];
+    const double *p = partials + acc_static[acc] * batch + (long long)b * U;
+    for (int u = g; u < U; u += (1 << gl)) s += p[u];
   }
   s = seg_sum_dpp(s, gl);
   if (valid && g == (1 << gl) - 1) A[o] = s;
 }
+#endif
 
 // weight gradients: sum over samples of the accumulator combinations; one
 // group of 2^gl lanes per weight, lanes striding over the batch

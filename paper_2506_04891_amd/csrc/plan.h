@@ -78,13 +78,25 @@ struct DevStage {
 };
 
 // One diagonal op's tables: TL indexed by (tile bits 0..h-1, extra bits),
-// TH by tile bits h..K-1; built per workgroup from the term list.
+// TH by tile bits h..K-1.  Tables of ops whose angles are shared by every
+// sample are built once per call for every tile position of the pass
+// (k_diag_tables) and copied to LDS; ops with per-sample angles are built per
+// workgroup from the term list.
 struct DevDiag {
   int32_t term_begin, term_end;
   int32_t h;                        // split point in tile bits
   int32_t n_extra;
   int32_t extra[MAX_DIAG_EXTRA];    // tile-bit indices (>= h) appended to TL's index
   int32_t lds_off;                  // table offset in the diag-table LDS area (complex elements)
+  int32_t gtab;                     // shared ops: offset of tile 0's tables in the prebuilt table
+                                    // area (complex elements), TL then TH per tile; -1 otherwise
+  int32_t pad[3];
+};
+
+// One shared diagonal op whose tables k_diag_tables builds: its pass, its
+// index in the diagonal table, and the number of tile positions (log2).
+struct DiagJob {
+  int32_t pass, diag, tiles_log, entries;
 };
 
 // Diagonal term: phase e^{i phi(v)} with v = bit values (first bit more significant).
@@ -157,7 +169,7 @@ struct DevPass {
   int32_t stage_begin;       // index into the stage table
   int32_t n_diag, diag_begin;
   int32_t n_acc;             // gradient accumulators of this pass
-  int32_t acc_region;        // offset of this pass's partials (floats)
+  int32_t acc_region;        // offset of this pass's partials (doubles)
   int32_t grad_stage_begin, n_grad_stages;   // backward-only tail stages (embed gradients)
   int32_t skip_bwd_store;    // backward of the first pass need not store
   int32_t diag_lds;          // complex elements of diag tables (and dense scratch) in LDS
@@ -211,7 +223,7 @@ struct AccInfo {        // where a global accumulator's partials live
 };
 
 struct PassGeom {       // per pass, for the finalize reduction
-  int32_t region;       // float offset of the pass's partials
+  int32_t region;       // offset (doubles) of the pass's partials
   int32_t n_wg;         // workgroups per launch (for the batch it was planned with) -- set at launch
   int32_t n_seg;        // segments per workgroup
   int32_t segs_per_sample;

@@ -949,6 +949,8 @@ static std::string emit(Plan &P) {
   P.dstage.clear();
   P.dop.clear();
   P.ddiag.clear();
+  P.diag_jobs.clear();
+  P.n_diag_tab = 0;
   P.dterm.clear();
   P.dtgrad.clear();
   P.dperm.clear();
@@ -1251,7 +1253,22 @@ static std::string emit(Plan &P) {
           dg.n_extra = (int)extra.size();
           for (size_t k = 0; k < extra.size() && k < (size_t)MAX_DIAG_EXTRA; ++k) dg.extra[k] = extra[k];
           dg.lds_off = d.diag_lds;
-          d.diag_lds += (1 << (dg.h + dg.n_extra)) + (1 << (K - dg.h));
+          const int entries = (1 << (dg.h + dg.n_extra)) + (1 << (K - dg.h));
+          d.diag_lds += entries;
+          dg.gtab = -1;
+          if (!op.per_sample) {
+            // angles shared by every sample: tables built once per call for
+            // each tile position of the pass
+            const int tiles_log = P.nv > K ? P.nv - K : 0;
+            dg.gtab = (int)P.n_diag_tab;
+            P.n_diag_tab += (long long)entries << tiles_log;
+            DiagJob j;
+            j.pass = (int)P.dpass.size();
+            j.diag = (int)P.ddiag.size();
+            j.tiles_log = tiles_log;
+            j.entries = entries;
+            P.diag_jobs.push_back(j);
+          }
           diag_index[oi_ir] = (int)P.ddiag.size() - d.diag_begin;
           P.ddiag.push_back(dg);
           d.n_diag++;
@@ -1531,6 +1548,49 @@ std::string build_plan(Plan &P, int n, const LayerSpec *layers, int n_layers, in
   return emit(P);
 }
 
+// Parameters read by an IR op (weights or features; fixed gates have none).
+static int op_params(const Plan &P, const IrOp &op) {
+  int k = 0;
+  for (int fi : op.factors)
+    if (is_param(P.factors[fi].gate) && P.factors[fi].src != SRC_FIXED) ++k;
+  for (const IrTerm &t : op.terms)
+    if (is_param(P.factors[t.factor].gate) && P.factors[t.factor].src != SRC_FIXED) ++k;
+  return k;
+}
+
+void pass_flops(const Plan &P, int pass, double *fwd, double *bwd) {
+  const PlanPass &pp = P.passes[pass];
+  double f = 0.0, g = 0.0;
+  for (int oi : pp.ops) {
+    const IrOp &op = P.ops[oi];
+    double of = 0.0;
+    switch (op.kind) {
+      case IR_U1: of = op.diagonal ? 6.0 : (op.real ? 8.0 : 16.0); break;
+      case IR_U2: {
+        const int gt = op.factors.empty() ? -1 : P.factors[op.factors[0]].gate;
+        if (gt == CNOT || gt == SWAP) of = 0.0;
+        else if (gt == CZ) of = 0.5;
+        else if (gt == ZZ) of = 6.0;
+        else if (gt == MS || gt == ECR) of = 6.0;
+        else of = 32.0;
+        break;
+      }
+      case IR_DIAG: of = 6.0; break;
+      case IR_DENSE: of = 8.0 * (double)(1 << P.nv); break;
+      default: of = 0.0; break;   // permutations, gradient-only sums
+    }
+    f += of;
+    g += 2.0 * of + 2.0 * op_params(P, op);
+  }
+  // embedding gradients taken at the end of this pass's backward
+  for (const std::vector<int> *ws : {&pp.grad_wires, &pp.outside_wires})
+    for (int w : *ws)
+      for (int fi : P.embed[w])
+        if (is_param(P.factors[fi].gate) && P.factors[fi].src != SRC_FIXED) g += 2.0;
+  if (fwd) *fwd = f;
+  if (bwd) *bwd = g;
+}
+
 std::string describe_plan(const Plan &P) {
   std::ostringstream o;
   o << "{\"n\":" << P.n << ",\"dtype\":\"" << (P.dtype ? "c128" : "c64") << "\",\"mode\":\""
@@ -1568,8 +1628,10 @@ std::string describe_plan(const Plan &P) {
       << ",\"u1_groups\":" << ngrp << ",\"u2\":" << nu2 << ",\"diag\":" << ndg << ",\"perm\":" << npm
       << ",\"dense\":" << ndense
       << ",\"grad_wires\":"
-      << pp.grad_wires.size() << ",\"outside_wires\":" << pp.outside_wires.size() << ",\"n_acc\":" << d.n_acc
-      << "}";
+      << pp.grad_wires.size() << ",\"outside_wires\":" << pp.outside_wires.size() << ",\"n_acc\":" << d.n_acc;
+    double ff = 0, fb = 0;
+    pass_flops(P, (int)p, &ff, &fb);
+    o << ",\"flops_per_amp_fwd\":" << ff << ",\"flops_per_amp_bwd\":" << fb << "}";
   }
   o << "]}";
   return o.str();

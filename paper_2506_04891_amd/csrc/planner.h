@@ -70,6 +70,8 @@ struct Plan {
   std::vector<DevStage> dstage;
   std::vector<DevOp> dop;
   std::vector<DevDiag> ddiag;
+  std::vector<DiagJob> diag_jobs;        // shared diagonal ops whose tables are prebuilt per call
+  long long n_diag_tab = 0;              // complex elements of the prebuilt tables
   std::vector<DevTerm> dterm;
   std::vector<DevTermGrad> dtgrad;
   std::vector<DevPerm> dperm;
@@ -105,5 +107,14 @@ std::string build_plan(Plan &P, int n, const LayerSpec *layers, int n_layers, in
                        int tile_bits);
 
 std::string describe_plan(const Plan &P);
+
+// Algorithmic flops per amplitude of pass `pass`, forward and backward: a
+// complex 2x2 16, a real 2x2 8, a diagonal layer (one phase multiply) 6, MS and
+// ECR 6 (their structured form), CZ 0.5, CNOT / SWAP / permutations 0, a general
+// 4x4 32, a full-layer unitary 8 * 2^nv; the backward is twice the forward
+// (psi and lambda are both uncomputed) plus one multiply-add (2 flops) per
+// parameter, embedding gradients included.  This is the arithmetic the
+// method needs, not the instructions issued.
+void pass_flops(const Plan &P, int pass, double *fwd, double *bwd);
 
 }  // namespace tqs

@@ -64,6 +64,7 @@ struct tqs_circuit {
   DevStage *d_stage = nullptr;
   DevOp *d_op = nullptr;
   DevDiag *d_diag = nullptr;
+  DiagJob *d_djob = nullptr;
   DevTerm *d_term = nullptr;
   DevPerm *d_perm = nullptr;
   DevGroup *d_group = nullptr;
@@ -120,6 +121,7 @@ tqs_status upload(tqs_circuit *c) {
       {P.dstage.data(), bytes_of(P.dstage), (void **)&c->d_stage},
       {P.dop.data(), bytes_of(P.dop), (void **)&c->d_op},
       {P.ddiag.data(), bytes_of(P.ddiag), (void **)&c->d_diag},
+      {P.diag_jobs.data(), bytes_of(P.diag_jobs), (void **)&c->d_djob},
       {P.dterm.data(), bytes_of(P.dterm), (void **)&c->d_term},
       {P.dperm.data(), bytes_of(P.dperm), (void **)&c->d_perm},
       {P.dgroup.data(), bytes_of(P.dgroup), (void **)&c->d_group},
@@ -149,10 +151,12 @@ tqs_status upload(tqs_circuit *c) {
 }
 
 struct WsLayout {
-  size_t x = 0, la = 0, lb = 0, mats = 0, mats_ps = 0, dbl = 0, dbl_ps = 0, partials = 0, A = 0, ev = 0;
+  size_t x = 0, la = 0, lb = 0, mats = 0, mats_ps = 0, dbl = 0, dbl_ps = 0, dtab = 0, partials = 0, A = 0, ev = 0;
   size_t total = 0;
   bool has_x = false, has_lb = false;
 };
+
+size_t expval_partials_bytes(const Plan &P, int B);
 
 WsLayout layout(const Plan &P, int B, bool grad) {
   WsLayout L;
@@ -173,12 +177,12 @@ WsLayout layout(const Plan &P, int B, bool grad) {
   L.mats_ps = take((size_t)B * P.n_mats_ps * es);
   L.dbl = take((size_t)P.n_dbl * 8);
   L.dbl_ps = take((size_t)B * P.n_dbl_ps * 8);
+  L.dtab = take((size_t)P.n_diag_tab * es);
   if (grad) {
-    L.partials = take((size_t)B * (size_t)P.units_total * (P.dtype ? 8 : 4));
+    L.partials = take((size_t)B * (size_t)P.units_total * sizeof(double));
     L.A = take((size_t)P.n_acc * B * 8);
   }
-  const size_t ev_units = P.n > KE ? ((size_t)1 << (P.n - KE)) : 1;
-  L.ev = take((size_t)B * ev_units * (KE + 1) * 8);
+  L.ev = take(expval_partials_bytes(P, B));
   L.total = off;
   return L;
 }
@@ -238,47 +242,6 @@ struct ProfScope {
   }
 };
 
-// Algorithmic flops of one op application on one amplitude (forward): a
-// complex multiply is 6 flops, a complex add 2.  U1: two complex products and
-// one add per output (14), real matrix 6, diagonal 6; U2 dense: four products
-// and three adds (30), MS 6, ECR 6 (two complex adds and one scaling), CZ 2,
-// CNOT / SWAP 0; split-table diagonal: two complex products (12).
-double op_flops(const DevOp &o) {
-  switch (o.kind) {
-    case OP_U1: return (o.flags & F_DIAGONAL) ? 6.0 : ((o.flags & F_REAL) ? 6.0 : 14.0);
-    case OP_U2:
-      switch (o.sub) {
-        case U2_CNOT: case U2_SWAP: return 0.0;
-        case U2_CZ: return 2.0;
-        case U2_MS: case U2_ECR: case U2_DIAG: return 6.0;
-        default: return 30.0;
-      }
-    case OP_DIAG: return 12.0;
-    default: return 0.0;
-  }
-}
-
-// Dense op: 2^nv complex multiply-adds per amplitude.
-double dense_flops(int nv) { return 8.0 * (double)(1 << nv); }
-
-// Gradient sums per amplitude.  A Pauli sum Im<l|P|p> needs one real term per
-// amplitude, l.x p.y - l.y p.x (or the real part for Y): two multiplies, one
-// add and the accumulation, 4 flops.  A single-qubit gate takes three sums, a
-// pair gate one; a diagonal layer takes w = Im(conj(l) p) (3 flops) and its
-// parity sums by a 16-point Walsh-Hadamard transform (4 adds per amplitude).
-constexpr double GRAD_U1_FLOPS = 12.0, GRAD_U2_FLOPS = 4.0, GRAD_DIAG_FLOPS = 7.0;
-
-// Backward flops of an op per amplitude: psi and lambda are both uncomputed
-// (2x forward; a diagonal layer's phase is formed once for both, 6 + 2 x 6)
-// and ops with parameters add their gradient sums.
-double op_flops_bwd(const DevOp &o) {
-  if (o.kind == OP_DIAG) return 18.0 + ((o.flags & F_GRAD) ? GRAD_DIAG_FLOPS : 0.0);
-  double f = 2.0 * op_flops(o);
-  if (o.flags & F_GRAD) f += (o.kind == OP_U1) ? GRAD_U1_FLOPS : GRAD_U2_FLOPS;
-  return f;
-}
-
-
 template <typename T, bool BWD>
 tqs_status launch_pass(tqs_circuit *c, int pi, int B, const cplx<T> *src0, cplx<T> *dst0,
                        const cplx<T> *src1, cplx<T> *dst1, char *ws, const WsLayout &L,
@@ -301,11 +264,12 @@ tqs_status launch_pass(tqs_circuit *c, int pi, int B, const cplx<T> *src0, cplx<
   a.dbl = kc(reinterpret_cast<const double *>(ws + L.dbl));
   a.dbl_ps = kc(reinterpret_cast<const double *>(ws + L.dbl_ps));
   a.dbl_ps_stride = P.n_dbl_ps;
+  a.diag_tabs = reinterpret_cast<const cplx<T> *>(ws + L.dtab);
   a.src0 = src0;
   a.dst0 = dst0;
   a.src1 = src1;
   a.dst1 = dst1;
-  a.partials = BWD ? reinterpret_cast<T *>(ws + L.partials) : nullptr;
+  a.partials = BWD ? reinterpret_cast<double *>(ws + L.partials) : nullptr;
   a.acc_region = (long long)B * P.pass_prefix[pi];
   a.units = P.pass_units[pi];
   a.batch = B;
@@ -321,39 +285,9 @@ tqs_status launch_pass(tqs_circuit *c, int pi, int B, const cplx<T> *src0, cplx<
       bytes = amps * es * ((g_init ? 1.0 : 2.0) + (d.skip_bwd_store ? 0.0 : 2.0));
     else
       bytes = amps * es * ((d.load_mode == LOAD_GLOBAL ? 1.0 : 0.0) + 1.0);
-    double f = 0;
-    for (int st = d.stage_begin; st < d.stage_begin + d.n_stages; ++st)
-      for (int oi = P.dstage[st].op_begin; oi < P.dstage[st].op_end; ++oi) {
-        if (P.dop[oi].kind == OP_DENSE) {
-          f += (BWD ? 2.0 : 1.0) * dense_flops(P.nv);
-        } else if (P.dop[oi].kind == OP_SEQ) {
-          // two pair gates, four 2x2, [one pair gate, [two 2x2]]
-          const DevSeq &q = P.dseq[P.dop[oi].aux];
-          for (int k = 0; k < SEQ_SLOTS; ++k) {
-            if (q.mat[k] < 0) continue;
-            const bool pair = k < 2 || k == 6;
-            if (pair)
-              f += BWD ? 12.0 + (q.acc[k] >= 0 ? GRAD_U2_FLOPS : 0.0) : 6.0;
-            else
-              f += BWD ? 28.0 + (q.acc[k] >= 0 ? GRAD_U1_FLOPS : 0.0) : 14.0;
-          }
-        } else if (P.dop[oi].kind == OP_U2G) {
-          // two structured pair gates (6 flop/amp each) and their gradient sums
-          const DevGroup &g = P.dgroup[P.dop[oi].aux];
-          for (int r = 0; r < 2; ++r) f += BWD ? 12.0 + (g.acc[r] >= 0 ? GRAD_U2_FLOPS : 0.0) : 6.0;
-        } else if (P.dop[oi].kind == OP_U1G) {
-          // each member: a complex 2x2 (14 flop/amp), backward twice that plus
-          // its Pauli sums when it has parameters
-          const DevGroup &g = P.dgroup[P.dop[oi].aux];
-          for (int r = 0; r < RB; ++r)
-            if (g.mat[r] >= 0) f += BWD ? 28.0 + (g.acc[r] >= 0 ? GRAD_U1_FLOPS : 0.0) : 14.0;
-        } else
-          f += BWD ? op_flops_bwd(P.dop[oi]) : op_flops(P.dop[oi]);
-      }
-    if (BWD)
-      for (int st = d.grad_stage_begin; st < d.grad_stage_begin + d.n_grad_stages; ++st)
-        for (int oi = P.dstage[st].op_begin; oi < P.dstage[st].op_end; ++oi)
-          f += P.dop[oi].kind == OP_GRAD1 ? GRAD_U1_FLOPS : GRAD_U2_FLOPS;
+    double ff = 0, fb = 0;
+    pass_flops(P, pi, &ff, &fb);
+    const double f = BWD ? fb : ff;
     flops = amps * f;
   }
   ProfScope ps(c, s, std::string(BWD ? "pass_bwd_K" : "pass_fwd_K") + std::to_string(d.K) +
@@ -371,7 +305,7 @@ template <typename T>
 tqs_status do_prep(tqs_circuit *c, int B, const double *w, const double *x, char *ws, const WsLayout &L,
                    hipStream_t s) {
   const Plan &P = c->plan;
-  if (P.prep.empty()) return TQS_OK;
+  if (P.prep.empty() && P.diag_jobs.empty()) return TQS_OK;
   PrepArgs<T> a;
   a.items = kc(c->d_prep);
   a.factors = kc(c->d_fac);
@@ -389,8 +323,22 @@ tqs_status do_prep(tqs_circuit *c, int B, const double *w, const double *x, char
   a.nv = P.nv;
   dim3 grid((B + 63) / 64, (unsigned)P.prep.size());
   ProfScope ps(c, s, "prep", 0.0, 0.0);
-  hipLaunchKernelGGL((k_prep<T>), grid, dim3(64), 0, s, a);
-  if (P.dense) hipLaunchKernelGGL((k_prep_dense<T>), dim3(1u << P.nv, (unsigned)P.prep.size()), dim3(64), 0, s, a);
+  if (!P.prep.empty()) hipLaunchKernelGGL((k_prep<T>), grid, dim3(64), 0, s, a);
+  if (P.dense && !P.prep.empty()) hipLaunchKernelGGL((k_prep_dense<T>), dim3(1u << P.nv, (unsigned)P.prep.size()), dim3(64), 0, s, a);
+  if (!P.diag_jobs.empty()) {
+    // split phase tables of the diagonal ops with shared angles, every tile position
+    DiagTabArgs<T> t;
+    t.passes = kc(c->d_pass);
+    t.diags = kc(c->d_diag);
+    t.terms = kc(c->d_term);
+    t.jobs = kc(c->d_djob);
+    t.dbl = kc(reinterpret_cast<const double *>(ws + L.dbl));
+    t.out = reinterpret_cast<cplx<T> *>(ws + L.dtab);
+    long long most = 1;
+    for (const DiagJob &j : P.diag_jobs) most = std::max(most, (long long)j.entries << j.tiles_log);
+    hipLaunchKernelGGL((k_diag_tables<T>), dim3((unsigned)((most + 255) / 256), (unsigned)P.diag_jobs.size()),
+                       dim3(256), 0, s, t);
+  }
   ps.end();
   HIP_TRY(hipGetLastError());
   return TQS_OK;
@@ -423,21 +371,32 @@ tqs_status forward_t(tqs_circuit *c, int B, const double *w, const double *x, vo
   return TQS_OK;
 }
 
+// Bytes of readout partials that <Z_i> and the norm need for `B` samples:
+// [B][units][KE + 1] doubles, units = 2^(n - KE) per sample (one below that).
+size_t expval_partials_bytes(const Plan &P, int B) {
+  const size_t ev_units = P.n > KE ? ((size_t)1 << (P.n - KE)) : 1;
+  return (size_t)B * ev_units * (KE + 1) * sizeof(double);
+}
+
 template <typename T>
-tqs_status expval_t(const tqs_circuit *c, int B, const void *state, double *expz, double *norm, char *ws,
-                    const WsLayout &L, hipStream_t s) {
+tqs_status expval_t(const tqs_circuit *c, int B, const void *state, double *expz, double *norm, double *partials,
+                    hipStream_t s, bool prof = true) {
   const Plan &P = c->plan;
   ReadArgs<T> a;
   a.psi = reinterpret_cast<const cplx<T> *>(state);
   a.lam = nullptr;
   a.g = nullptr;
-  a.partials = reinterpret_cast<double *>(ws + L.ev);
+  a.partials = partials;
   a.n = P.n;
   a.batch = B;
   const long long padded = (long long)B << P.nv;
   const long long blocks = (padded + (1ll << KE) - 1) >> KE;
-  ProfScope ps(const_cast<tqs_circuit *>(c), s, "expval", (double)B * (double)(1ll << P.n) * sizeof(cplx<T>),
-               (double)B * (double)(1ll << P.n) * 8.0);
+  tqs_circuit *cm = const_cast<tqs_circuit *>(c);
+  const bool was = cm->profile;
+  if (!prof) cm->profile = false;
+  ProfScope ps(cm, s, "expval", (double)B * (double)(1ll << P.n) * sizeof(cplx<T>),
+               (double)B * (double)(1ll << P.n) * (4.0 + P.n));   // |psi|^2 and n signed sums
+  if (!prof) cm->profile = was;
   if (P.nv >= KE)
     hipLaunchKernelGGL((k_expval<T, true>), dim3((unsigned)blocks), dim3(NTE), 0, s, a);
   else
@@ -447,7 +406,7 @@ tqs_status expval_t(const tqs_circuit *c, int B, const void *state, double *expz
   const long long tot = (long long)B * (P.n + 1);
   const int gl = std::min(6, std::max(0, P.n - KE));   // lanes per output: the unit count, up to 64
   hipLaunchKernelGGL(k_expval_final, dim3((unsigned)(((tot << gl) + NTR - 1) / NTR)), dim3(NTR), 0, s,
-                     (const double *)(ws + L.ev), expz, norm, P.n, B, gl);
+                     (const double *)partials, expz, norm, P.n, B, gl);
   HIP_TRY(hipGetLastError());
   return TQS_OK;
 }
@@ -504,8 +463,8 @@ tqs_status adjoint_t(tqs_circuit *c, int B, const double *w, const double *x, vo
   if (P.n_acc > 0) {
     const long long tot = (long long)P.n_acc * B;
     const int gl = ceil_log2(c->max_units);
-    hipLaunchKernelGGL((k_acc_reduce<T>), dim3((unsigned)(((tot << gl) + NTR - 1) / NTR)), dim3(NTR), 0, s,
-                       reinterpret_cast<const T *>(ws + L.partials), (const long long *)c->d_acc_static,
+    hipLaunchKernelGGL(k_acc_reduce, dim3((unsigned)(((tot << gl) + NTR - 1) / NTR)), dim3(NTR), 0, s,
+                       reinterpret_cast<const double *>(ws + L.partials), (const long long *)c->d_acc_static,
                        (const int *)c->d_acc_units, P.n_acc, B, A, gl);
     HIP_TRY(hipGetLastError());
   }
@@ -643,8 +602,9 @@ tqs_status tqs_expval_z(const tqs_circuit *c, int32_t batch, const void *state_d
   const WsLayout L = layout(c->plan, batch, false);
   if (ws_bytes < L.total) return fail(TQS_ENOMEM, "workspace too small");
   char *ws = static_cast<char *>(ws_d);
-  if (c->dtype == TQS_C64) return expval_t<float>(c, batch, state_d, expz_d, norm_d, ws, L, (hipStream_t)s);
-  return expval_t<double>(c, batch, state_d, expz_d, norm_d, ws, L, (hipStream_t)s);
+  double *part = reinterpret_cast<double *>(ws + L.ev);
+  if (c->dtype == TQS_C64) return expval_t<float>(c, batch, state_d, expz_d, norm_d, part, (hipStream_t)s);
+  return expval_t<double>(c, batch, state_d, expz_d, norm_d, part, (hipStream_t)s);
 }
 
 tqs_status tqs_adjoint_grad(tqs_circuit *c, int32_t batch, const double *weights_d, const double *features_d,

@@ -179,12 +179,14 @@ class Server:
                 raise TimeoutError("serving queue did not drain")
             time.sleep(self.poll_s)
 
-    def stats(self):
-        lat = np.array([r.t_done - r.t_arrive for r in self.completed]) if self.completed else np.zeros(1)
-        evals = sum(r.batch for r in self.completed)
-        span = (max(r.t_done for r in self.completed) - min(r.t_arrive for r in self.completed)
-                if self.completed else 0.0)
-        return {"requests": len(self.completed), "evals": evals,
+    def stats(self, min_rid=None):
+        """Latency percentiles and throughput of the completed requests (only
+        those with rid >= min_rid when given: a warm-up prefix is left out)."""
+        done = [r for r in self.completed if min_rid is None or (r.rid is not None and r.rid >= min_rid)]
+        lat = np.array([r.t_done - r.t_arrive for r in done]) if done else np.zeros(1)
+        evals = sum(r.batch for r in done)
+        span = (max(r.t_done for r in done) - min(r.t_arrive for r in done) if done else 0.0)
+        return {"requests": len(done), "evals": evals,
                 "p50_ms": float(np.percentile(lat, 50) * 1e3), "p99_ms": float(np.percentile(lat, 99) * 1e3),
                 "mean_ms": float(lat.mean() * 1e3), "evals_per_s": evals / span if span > 0 else 0.0,
                 "launches": self.launches, "peak_reserved_bytes": self.peak_reserved,

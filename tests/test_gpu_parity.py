@@ -272,6 +272,25 @@ def test_rz_ry_cnot_vq_qdi(encoding, n, dtype, mode, B):
 
 
 @pytest.mark.parametrize("encoding", ["vq", "qdi"])
+@pytest.mark.parametrize("circuit", ["ionq", "ibm"])
+@pytest.mark.parametrize("n,dtype,mode,B", [
+    (4, "c128", "auto", 5), (4, "c64", "dense", 3), (6, "c128", "per_layer", 3), (8, "c64", "fused", 4),
+    (10, "c128", "fused", 2), (12, "c64", "per_layer", 3), (14, "c64", "fused", 3), (16, "c64", "fused", 2),
+    (16, "c128", "fused", 1),
+])
+def test_native_vq_qdi(circuit, encoding, n, dtype, mode, B):
+    """The IonQ and IBM native-gate circuits of App. B with the encoding pair
+    once (VQ) or opening every block (QDI, the same features re-uploaded)."""
+    build = W.circuit_ionq if circuit == "ionq" else W.circuit_ibm
+    layers = build(n, 8, encoding)
+    w, x, g = _params(n, layers, B, seed=40 + n, dist="uniform2pi")
+    note(f"case native {circuit} {encoding} n={n} {dtype} mode={mode} B={B}")
+    got = gpu_run(_circuit(n, layers, dtype, mode), w, x, g)
+    ref = oracle_run(n, layers, w, x, g)
+    compare(got, ref, dtype, label=f"native {circuit} {encoding} n={n} {mode}")
+
+
+@pytest.mark.parametrize("encoding", ["vq", "qdi"])
 def test_rz_ry_cnot_16q_b64_sampled(encoding):
     """Fig. 8's batch-64 shape at 16 qubits, whole batch on the GPU, sampled
     rows against the oracle."""

@@ -391,30 +391,41 @@ def test_rz_before_readout_has_zero_gradient():
     np.testing.assert_allclose(gw, 0.0, atol=1e-14)
 
 
-def _untied_qdi(n, blocks):
-    """The QDI circuit with a separate feature column block per RZ layer."""
+def _untied(n, layers):
+    """The same circuit with a separate feature column block per INPUT layer."""
     out, k = [], 0
-    for ly in W.circuit_rz_ry_cnot(n, blocks, "qdi"):
+    for ly in layers:
         if ly.source == "INPUT":
             ly = ly._replace(offset=k * n)
             k += 1
         out.append(ly)
-    return out
+    return out, k
 
 
-@pytest.mark.parametrize("n", [3, 4])
-def test_qdi_reuploaded_feature_gradient(n):
-    """Sec. 3, QDI encoding: the features enter every RZ layer, so dL/dx_q is
-    the sum over blocks of the gradients of a circuit whose RZ layers have
-    their own copies of x (the chain rule for a shared input), and it agrees
-    with central differences of the tied circuit."""
+QDI_CIRCUITS = [
+    ("rz_ry_cnot", lambda n, blocks: W.circuit_rz_ry_cnot(n, blocks, "qdi"), "normal"),
+    ("ionq", lambda n, blocks: W.circuit_ionq(n, blocks, "qdi"), "uniform2pi"),
+    ("ibm", lambda n, blocks: W.circuit_ibm(n, blocks, "qdi"), "uniform2pi"),
+]
+
+
+@pytest.mark.parametrize("case", QDI_CIRCUITS, ids=[c[0] for c in QDI_CIRCUITS])
+@pytest.mark.parametrize("n", [2, 4])
+def test_qdi_reuploaded_feature_gradient(case, n):
+    """QDI encoding (Sec. 3 for the Fig. 6 circuit, App. B for the native-gate
+    circuits): the features enter every encoding layer, so dL/dx_q is the sum
+    over blocks of the gradients of a circuit whose encoding layers have their
+    own copies of x (the chain rule for a shared input), and it agrees with
+    central differences of the tied circuit."""
+    _, build, dist = case
     blocks = 3
-    layers = W.circuit_rz_ry_cnot(n, blocks, "qdi")
+    layers = build(n, blocks)
     assert W.circuit_counts(n, layers)[1] == n
-    w, x = W.draw_params(n, layers, 2, "normal", 21)
+    w, x = W.draw_params(n, layers, 2, dist, 21)
     g = W.upstream(2, n, "normal", 4)
     e, gw, gx = sim.grad_adjoint(n, layers, w, x, g)
-    untied = _untied_qdi(n, blocks)
+    untied, k = _untied(n, layers)
+    assert k == blocks
     xu = np.tile(x, (1, blocks))
     eu, gwu, gxu = sim.grad_adjoint(n, untied, w, xu, g)
     np.testing.assert_allclose(e, eu, atol=1e-14)
@@ -427,6 +438,19 @@ def test_qdi_reuploaded_feature_gradient(n):
     # block's share would fail the sum above
     per_block = gxu.reshape(2, blocks, n)
     assert np.max(np.abs(per_block[:, 0] - gx)) > 1e-3
+
+
+def test_native_qdi_reuploads_every_block():
+    """App. B QDI form: each block opens with the encoding pair, so the
+    native-gate circuits hold one RZ(x) layer per block, all reading the same
+    n feature columns."""
+    for build, lead in ((W.circuit_ionq, "GPI2"), (W.circuit_ibm, "SX")):
+        layers = build(6, 4, "qdi")
+        enc = [i for i, ly in enumerate(layers) if ly.source == "INPUT"]
+        assert len(enc) == 4
+        assert all(layers[i].gate == "RZ" and layers[i].offset == 0 for i in enc)
+        assert all(layers[i - 1].gate == lead for i in enc)
+        assert len([ly for ly in build(6, 4, "vq") if ly.source == "INPUT"]) == 1
 
 
 def test_vq_encodes_first_rz_only():
