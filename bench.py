@@ -61,6 +61,10 @@ def parse():
     p.add_argument("--dispatch-sweep", action="store_true")
     p.add_argument("--memory-sweep", action="store_true",
                    help="device memory of one forward + adjoint call vs qubits (QDI circuit)")
+    p.add_argument("--technique-sweep", action="store_true",
+                   help="forward time of one layer of each kind under each layer technique, n = 4..20")
+    p.add_argument("--backward-sweep", action="store_true",
+                   help="adjoint vs stored-state backward on the benchmark workloads")
     p.add_argument("--vq-qdi-sweep", action="store_true",
                    help="forward/backward/total time vs qubits for the VQ and QDI encodings")
     return p.parse_args()
@@ -421,13 +425,14 @@ def vq_qdi_sweep(iters=20):
                 print(json.dumps(row), flush=True)
 
 
-def memory_sweep():
-    """Fig. 9's measurement on the QDI circuit of Fig. 6 (8 blocks, c64): the
-    device memory of one forward + <Z_i> + adjoint call against the number of
-    qubits at batch 1 and 100.  Reported: the library's workspace query, the
-    state, and the peak the caching allocator saw during the call (all
-    buffers the call needs); beside them, the states a per-layer
-    stored-state backpropagation would keep (computed, (L+1) states)."""
+def memory_sweep(iters=10):
+    """Fig. 9's measurement on the QDI circuit of Fig. 6 (8 blocks, c64), for
+    both backward modes: the device memory of one forward + <Z_i> + backward
+    call against the number of qubits at batch 1 and 100 -- the peak the
+    caching allocator saw during the call (state, workspace, parameters,
+    outputs), measured, beside the library's workspace query -- and the time
+    per call.  "adjoint" uncomputes psi; "stored" keeps every forward pass's
+    output (the paper's stored-state backpropagation at pass granularity)."""
     import torch
     import workloads as W
     from paper_2506_04891_amd import tqsim as T
@@ -435,27 +440,133 @@ def memory_sweep():
     for B in (1, 100):
         for n in range(4, 23, 2):
             layers = W.circuit_rz_ry_cnot(n, 8, "qdi")
-            c = T.Circuit(n, layers, "c64")
-            w, x = W.draw_params(n, layers, B, "normal", 0)
-            torch.cuda.synchronize()
-            torch.cuda.empty_cache()
-            torch.cuda.reset_peak_memory_stats()
-            base = torch.cuda.memory_allocated()
+            for bwd in ("adjoint", "stored"):
+                c = T.Circuit(n, layers, "c64", backward=bwd)
+                if bwd == "stored" and c.workspace_size(B, True) > (96 << 30):
+                    continue
+                w, x = W.draw_params(n, layers, B, "normal", 0)
+                torch.cuda.synchronize()
+                torch.cuda.empty_cache()
+                torch.cuda.reset_peak_memory_stats()
+                base = torch.cuda.memory_allocated()
+                wt, xt = torch.tensor(w, device=dev), torch.tensor(x, device=dev)
+                g = torch.ones((B, n), dtype=torch.float64, device=dev)
+                st = torch.empty((B, 2 ** n), dtype=c.complex_dtype, device=dev)
+                ws = c.workspace(B, True, dev)
+
+                def step():
+                    c.forward(wt, xt, state=st, ws=ws)
+                    c.expval_z(st, ws=ws)
+                    return c.adjoint_grad(wt, xt, st, g, ws=ws)
+                gw, gx = step()
+                torch.cuda.synchronize()
+                peak = torch.cuda.max_memory_allocated() - base
+                for _ in range(2):
+                    step()
+                torch.cuda.synchronize()
+                e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                e0.record()
+                for _ in range(iters):
+                    step()
+                e1.record()
+                torch.cuda.synchronize()
+                state = B * (8 << n)
+                passes = len([p for p in c.plan()["passes"] if not p["bwd_only"]])
+                print(json.dumps({"encoding": "qdi", "backward": bwd, "batch": B, "n": n, "layers": len(layers),
+                                  "forward_passes": passes, "state_bytes": state,
+                                  "workspace_bytes": c.workspace_size(B, True), "peak_bytes": int(peak),
+                                  "peak_states": round(peak / state, 2),
+                                  "us_per_call": round(e0.elapsed_time(e1) / iters * 1e3, 1)}), flush=True)
+                del wt, xt, g, st, ws, gw, gx, c
+
+
+def technique_sweep(iters=20):
+    """The per-layer benchmark of Secs. 2.2-2.5 (Figs. 2-5) on this GPU: the
+    forward time of one layer of each kind under each technique the
+    dispatcher can select, in per-layer mode, against the number of qubits,
+    at batch 1 and 64 (c64).  The circuit is RY(x) embedding, CNOT ring, then
+    the layer under test; the embedding-and-ring circuit alone is timed too,
+    so the layer's own time is the difference."""
+    import torch
+    import workloads as W
+    from paper_2506_04891_amd import tqsim as T
+    dev = torch.device("cuda")
+    lead = [W.L("RY", "ALL", "INPUT"), W.L("CNOT", "RING")]
+    kinds = {
+        "RX": ([W.L("RX", "ALL", "WEIGHT")], ("kron", "hrz")),
+        "RY": ([W.L("RY", "ALL", "WEIGHT")], ("kron", "hrz")),
+        "Rot": ([W.L("ROT", "ALL", "WEIGHT")], ("kron", "hrz")),
+        "GPI2": ([W.L("GPI2", "ALL", "WEIGHT")], ("kron", "hrz")),
+        "H": ([W.L("H", "ALL")], ("real", "fhwt")),
+        "RZ": ([W.L("RZ", "ALL", "WEIGHT")], ("tables", "einsum")),
+        "ZZ": ([W.L("ZZ", "RING", "WEIGHT")], ("tables", "einsum")),
+        "GPI": ([W.L("GPI", "ALL", "WEIGHT")], ("tables", "einsum")),
+        "CNOT": ([W.L("CNOT", "RING")], ("gather",)),
+    }
+    opts = {"kron": {}, "hrz": {"hrz": True}, "real": {"fhwt": False}, "fhwt": {"fhwt": True},
+            "tables": {"diag": "tables"}, "einsum": {"diag": "einsum"}, "gather": {}}
+
+    def fwd_us(layers, n, B, **kw):
+        c = T.Circuit(n, layers, "c64", mode="per_layer", **kw)
+        w, x = W.draw_params(n, layers, B, "normal", 0)
+        wt, xt = torch.tensor(w, device=dev), torch.tensor(x, device=dev)
+        st = torch.empty((B, 2 ** n), dtype=c.complex_dtype, device=dev)
+        ws = c.workspace(B, False, dev)
+        for _ in range(3):
+            c.forward(wt, xt, state=st, ws=ws)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(iters):
+            c.forward(wt, xt, state=st, ws=ws)
+        e1.record()
+        torch.cuda.synchronize()
+        return round(e0.elapsed_time(e1) / iters * 1e3, 2)
+
+    for B in (1, 64):
+        for n in (4, 6, 8, 10, 12, 14, 16, 18, 20):
+            base = fwd_us(lead, n, B)
+            for kind, (ly, techs) in kinds.items():
+                row = {"layer": kind, "n": n, "batch": B, "lead_us": base}
+                for t in techs:
+                    row[t + "_us"] = fwd_us(lead + ly, n, B, **opts[t])
+                print(json.dumps(row), flush=True)
+
+
+def backward_sweep(iters=10):
+    """Adjoint (uncompute) against stored-state backward on the benchmark
+    workloads: ms per forward + <Z_i> + backward step, and workspace bytes."""
+    import torch
+    import workloads as W
+    from paper_2506_04891_amd import tqsim as T
+    dev = torch.device("cuda")
+    for name in ("c2_12q_b256", "c4a_16q_b128_ionq", "c4b_16q_b128_ibm", "c3_20q_b32"):
+        n, B, dt, layers, w, x = W.config(name)
+        row = {"config": name}
+        for bwd in ("adjoint", "stored"):
+            c = T.Circuit(n, layers, dt, backward=bwd)
             wt, xt = torch.tensor(w, device=dev), torch.tensor(x, device=dev)
             g = torch.ones((B, n), dtype=torch.float64, device=dev)
             st = torch.empty((B, 2 ** n), dtype=c.complex_dtype, device=dev)
             ws = c.workspace(B, True, dev)
-            c.forward(wt, xt, state=st, ws=ws)
-            e = c.expval_z(st, ws=ws)
-            gw, gx = c.adjoint_grad(wt, xt, st, g, ws=ws)
+
+            def step():
+                c.forward(wt, xt, state=st, ws=ws)
+                c.expval_z(st, ws=ws)
+                c.adjoint_grad(wt, xt, st, g, ws=ws)
+            for _ in range(3):
+                step()
             torch.cuda.synchronize()
-            peak = torch.cuda.max_memory_allocated() - base
-            state = B * (8 << n)
-            print(json.dumps({"encoding": "qdi", "batch": B, "n": n, "layers": len(layers),
-                              "state_bytes": state, "workspace_bytes": c.workspace_size(B, True),
-                              "peak_bytes": int(peak),
-                              "stored_state_backprop_bytes": (len(layers) + 1) * state}), flush=True)
-            del wt, xt, g, st, ws, e, gw, gx, c
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            for _ in range(iters):
+                step()
+            e1.record()
+            torch.cuda.synchronize()
+            row[bwd + "_ms"] = round(e0.elapsed_time(e1) / iters, 4)
+            row[bwd + "_workspace_bytes"] = c.workspace_size(B, True)
+            del c, ws, st
+        print(json.dumps(row), flush=True)
 
 
 C4 = ("c4a_16q_b128_ionq", "c4b_16q_b128_ibm")
@@ -608,7 +719,8 @@ def main():
         sys.exit(2)
     # the CPU baselines run first: the pooled one forks, which must happen
     # before anything initialises the GPU in this process
-    sweep = a.dense_sweep or a.dispatch_sweep or a.vq_qdi_sweep or a.memory_sweep or a.serve_only
+    sweep = (a.dense_sweep or a.dispatch_sweep or a.vq_qdi_sweep or a.memory_sweep or a.serve_only
+             or a.backward_sweep or a.technique_sweep)
     cpu = None if (a.no_cpu_baseline or sweep) else cpu_baseline()
     ref, cpu_pool = ({}, None) if (a.no_cpu_baseline or sweep) else oracle_pool()
     import torch
@@ -628,6 +740,12 @@ def main():
         return
     if a.memory_sweep:
         memory_sweep()
+        return
+    if a.backward_sweep:
+        backward_sweep()
+        return
+    if a.technique_sweep:
+        technique_sweep()
         return
     if a.serve_only:
         print(json.dumps(serving_bench(a.serve_requests, a.serve_max_qubits,

@@ -56,12 +56,19 @@ typedef enum {
 
 typedef enum { TQS_C64 = 0, TQS_C128 = 1 } tqs_dtype;
 
-/* Gates of the paper's Table 1 / Appendix A (Rot is not provided). */
+/* Gates of the paper's Table 1 / Appendix A.  TQS_ROT is Appendix A's
+ * Rot(theta, phi, lambda) = [[c, -e^{i lambda} s], [e^{i phi} s, e^{i(phi+lambda)} c]]
+ * (c, s = cos, sin of theta/2; radians) and reads three parameters per gate.
+ * TQS_MS is MS(phi0, phi1, theta) = exp(-i pi theta P(phi1) (x) P(phi0)) with
+ * P(phi) = [[0, e^{-2 pi i phi}], [e^{2 pi i phi}, 0]]: its printed rows 0-2,
+ * entry (3, 0) read as e^{+2 pi i (phi0 + phi1)} (as printed it would not be
+ * unitary); the phases come from fixed_param2 / fixed_param3 (turns). */
 typedef enum {
   TQS_RX = 0, TQS_RY = 1, TQS_RZ = 2, TQS_H = 3, TQS_X = 4, TQS_Z = 5, TQS_S = 6,
   TQS_SX = 7, TQS_GPI = 8, TQS_GPI2 = 9,                       /* 1-qubit */
   TQS_CNOT = 10, TQS_CZ = 11, TQS_SWAP = 12, TQS_ZZ = 13, TQS_MS = 14,
-  TQS_ECR = 15                                                 /* 2-qubit */
+  TQS_ECR = 15,                                                /* 2-qubit */
+  TQS_ROT = 16                                                 /* 1-qubit, 3 parameters */
 } tqs_gate;
 
 typedef enum {
@@ -77,7 +84,8 @@ typedef enum {
   TQS_FIXED = 0,       /* every gate of the layer uses fixed_param                 */
   TQS_WEIGHT = 1,      /* gate k of the layer uses weights[offset + k]             */
   TQS_INPUT = 2        /* gate k uses features[b * n_features + offset + k]        */
-} tqs_source;
+} tqs_source;          /* TQS_ROT: gate k uses (theta, phi, lambda) at offset + 3k,
+                          + 3k + 1, + 3k + 2; FIXED: fixed_param, fixed_param2, 3 */
 
 typedef struct {
   int32_t gate;        /* tqs_gate                                                 */
@@ -87,6 +95,8 @@ typedef struct {
   int32_t wire2;       /* TQS_WIRE, 2-qubit gates: the second wire                 */
   int32_t offset;      /* first weight index / feature column of the layer         */
   double fixed_param;  /* parameter used when source == TQS_FIXED                  */
+  double fixed_param2; /* TQS_MS: phi0 (turns); TQS_ROT with TQS_FIXED: phi         */
+  double fixed_param3; /* TQS_MS: phi1 (turns); TQS_ROT with TQS_FIXED: lambda      */
 } tqs_layer;
 
 typedef struct tqs_circuit tqs_circuit;
@@ -156,10 +166,35 @@ tqs_status tqs_adjoint_grad(tqs_circuit *c, int32_t batch, const double *weights
  *                cores (the unitary operation of Sec. 2.2.1); for n > 6 the
  *                plan falls back to fused passes
  *   "tile_bits"  0 = auto, else K in [10, 12] for multi-pass plans
+ *   "hrz"        1 = H-Rz expansion (Sec. 2.5): RX, RY, GPI2 and Rot layers are
+ *                rewritten as layers of H, RZ and phase gates (RX = H RZ H;
+ *                RY = S H RZ H S^dag; GPI2(phi) = RZ(2 pi phi) H RZ(pi/2) H
+ *                RZ(-2 pi phi)), each then applied by its own technique
+ *   "fhwt"       1 (default) = Hadamard layers by the fast Walsh-Hadamard
+ *                transform (add / subtract butterflies, one scale, Sec. 2.5);
+ *                0 = as real 2x2 matrices
+ *   "diag"       0 (default) = diagonal layers by split eigenphase tables (the
+ *                eigenphase computation of Sec. 2.4.1 on the two halves of the
+ *                tile, combined as a diagonal tensor product, Sec. 2.4.2);
+ *                1 = diagonal Einsum (Sec. 2.4.3): gate by gate, one diagonal
+ *                factor per gate
  *   "profile"    1 = time every kernel launch with HIP events (any time; not
  *                to be used while the stream is being captured into a graph)
- * EINVAL for an unknown key or value, or for a plan key after the plan has
- * been uploaded. */
+ *   "backward"   0 = adjoint with uncompute (default): psi is rebuilt pass by
+ *                pass with the inverse layers, two state sets at any depth;
+ *                1 = stored states, the backpropagation of the paper's own
+ *                training (Sec. 2.1, Sec. 3): tqs_forward keeps the output of
+ *                every tile pass but the last in the workspace, and
+ *                tqs_adjoint_grad reads psi from there and writes back only
+ *                lambda -- it must get the workspace of the forward call, not
+ *                modified in between (tqs_expval_z may run in between);
+ *                2 = stored states when they fit "stored_cap" bytes for the
+ *                call's batch, adjoint otherwise (decided per batch size, the
+ *                same way by every call)
+ *   "stored_cap" bytes the stored states may take under backward = 2
+ *                (default 8 GiB)
+ * EINVAL for an unknown key or value, or for any key but "profile" after the
+ * plan has been uploaded. */
 tqs_status tqs_set_option(tqs_circuit *c, const char *key, int64_t value);
 
 /* Per-kernel-kind launch statistics gathered while "profile" is on: waits for

@@ -14,9 +14,15 @@ Readings of entries the source prints inconsistently
   (I (x) X - X (x) Y)/sqrt(2), which is unitary and squares to the identity;
   that matrix is used here.
 * MS (Appendix A, "Other gates"): for phi0 = phi1 = 0 every reading agrees on
-  MS(theta) = cos(pi theta) I - i sin(pi theta) X (x) X; only that case is
-  provided.
+  MS(theta) = cos(pi theta) I - i sin(pi theta) X (x) X.  With phases, the
+  printed rows 0-2 are those of exp(-i pi theta P(phi1) (x) P(phi0)), with
+  P(phi) = [[0, e^{-2 pi i phi}], [e^{2 pi i phi}, 0]] (the GPI matrix); the
+  printed entry (3, 0) carries e^{-2 pi i (phi0 + phi1)}, which makes the
+  matrix non-unitary, and is read as e^{+2 pi i (phi0 + phi1)} (MSP below).
 * GPI is treated as a parametrized gate (its Appendix A matrix depends on phi).
+* Rot(theta, phi, lambda) is Appendix A's single-qubit rotation (radians).  The
+  H-Rz decomposition printed for a "general rotation" in Sec. 2.5 describes a
+  different gate; it is not used.
 """
 from __future__ import annotations
 
@@ -108,7 +114,46 @@ def MS(t):
     return _c([[c, 0, 0, -1j * s], [0, c, -1j * s, 0], [0, -1j * s, c, 0], [-1j * s, 0, 0, c]])
 
 
+def ROT(theta, phi, lam):
+    """Rot(theta, phi, lambda) of Appendix A."""
+    c, s = np.cos(theta / 2), np.sin(theta / 2)
+    return _c([[c, -np.exp(1j * lam) * s], [np.exp(1j * phi) * s, np.exp(1j * (phi + lam)) * c]])
+
+
+def MSP(phi0, phi1, theta):
+    """MS(phi0, phi1, theta) of Appendix A (phases in turns), entry (3, 0) as read
+    above; MSP(0, 0, t) = MS(t)."""
+    c, s = np.cos(np.pi * theta), np.sin(np.pi * theta)
+    e = lambda a: np.exp(-2j * np.pi * a)
+    return _c([[c, 0, 0, -1j * e(phi0 + phi1) * s],
+               [0, c, -1j * e(phi1 - phi0) * s, 0],
+               [0, -1j * e(phi0 - phi1) * s, c, 0],
+               [-1j * e(-(phi0 + phi1)) * s, 0, 0, c]])
+
+
 # ---- analytic derivatives d U / d param ------------------------------------
+def dROT(theta, phi, lam):
+    """(dRot/dtheta, dRot/dphi, dRot/dlambda)."""
+    c, s = np.cos(theta / 2), np.sin(theta / 2)
+    ep, el, epl = np.exp(1j * phi), np.exp(1j * lam), np.exp(1j * (phi + lam))
+    d_t = _c([[-s / 2, -el * c / 2], [ep * c / 2, -epl * s / 2]])
+    d_p = _c([[0, 0], [1j * ep * s, 1j * epl * c]])
+    d_l = _c([[0, -1j * el * s], [0, 1j * epl * c]])
+    return d_t, d_p, d_l
+
+
+def dMSP(phi0, phi1, theta):
+    """dMS(phi0, phi1, theta) / dtheta."""
+    c, s = np.cos(np.pi * theta), np.sin(np.pi * theta)
+    e = lambda a: np.exp(-2j * np.pi * a)
+    p = np.pi
+    return _c([[-p * s, 0, 0, -1j * p * e(phi0 + phi1) * c],
+               [0, -p * s, -1j * p * e(phi1 - phi0) * c, 0],
+               [0, -1j * p * e(phi0 - phi1) * c, -p * s, 0],
+               [-1j * p * e(-(phi0 + phi1)) * c, 0, 0, -p * s]])
+
+
+
 def dRX(t):
     c, s = np.cos(t / 2), np.sin(t / 2)
     return _c([[-s / 2, -0.5j * c], [-0.5j * c, -s / 2]])
@@ -151,21 +196,43 @@ PARAM = {"RX": (RX, dRX), "RY": (RY, dRY), "RZ": (RZ, dRZ), "GPI": (GPI, dGPI),
          "GPI2": (GPI2, dGPI2), "ZZ": (ZZ, dZZ), "MS": (MS, dMS)}
 
 
-def matrix(gate: str, param=None):
-    """Gate matrix; ``param`` ignored for fixed gates."""
+# gates with several parameters: Rot reads (theta, phi, lambda)
+N_PARAMS = {"ROT": 3}
+
+
+def matrix(gate: str, param=None, phases=(0.0, 0.0)):
+    """Gate matrix; ``param`` ignored for fixed gates, a 3-sequence for Rot;
+    ``phases`` = (phi0, phi1) of MS."""
     if gate in FIXED:
         return FIXED[gate]()
+    if gate == "ROT":
+        return ROT(*param)
+    if gate == "MS" and tuple(phases) != (0.0, 0.0):
+        return MSP(phases[0], phases[1], param)
     return PARAM[gate][0](param)
+
+
+def dmatrices(gate: str, param, phases=(0.0, 0.0)):
+    """Derivatives of the matrix, one per parameter of the gate."""
+    if gate == "ROT":
+        return list(dROT(*param))
+    if gate == "MS" and tuple(phases) != (0.0, 0.0):
+        return [dMSP(phases[0], phases[1], param)]
+    return [PARAM[gate][1](param)]
 
 
 def dmatrix(gate: str, param):
     return PARAM[gate][1](param)
 
 
-def generator(gate: str, param):
-    """Output-side generator G = i (dU/dparam) U^dagger (Hermitian).
+def generators(gate: str, param, phases=(0.0, 0.0)):
+    """Output-side generators G_k = i (dU/dparam_k) U^dagger (Hermitian), one per
+    parameter.  With them the derivative of <psi|H|psi> through this gate is
+    2 Im <lambda|G_k|psi>, lambda and psi taken at the gate's output."""
+    U = matrix(gate, param, phases)
+    return [1j * d @ U.conj().T for d in dmatrices(gate, param, phases)]
 
-    With it the derivative of <psi|H|psi> through this gate is
-    2 Im <lambda|G|psi>, lambda and psi taken at the gate's output."""
-    U = matrix(gate, param)
-    return 1j * dmatrix(gate, param) @ U.conj().T
+
+def generator(gate: str, param):
+    """The generator of a one-parameter gate (see generators)."""
+    return generators(gate, param)[0]

@@ -23,8 +23,13 @@ import numpy as np
 
 from . import gates as G
 
-PARAM_GATES = tuple(G.PARAM)
-ONE_QUBIT = ("RX", "RY", "RZ", "H", "X", "Z", "S", "SX", "GPI", "GPI2")
+PARAM_GATES = tuple(G.PARAM) + ("ROT",)
+ONE_QUBIT = ("RX", "RY", "RZ", "H", "X", "Z", "S", "SX", "GPI", "GPI2", "ROT")
+
+
+def n_params(gate):
+    """Parameters one gate reads (Rot: theta, phi, lambda)."""
+    return G.N_PARAMS.get(gate, 1) if gate in PARAM_GATES else 0
 
 
 # ---------------------------------------------------------------------------
@@ -64,7 +69,7 @@ def param_counts(n, layers):
     nw = nf = 0
     for ly in layers:
         if ly.gate in PARAM_GATES and ly.source != "FIXED":
-            k = len(pattern_wires(n, ly))
+            k = n_params(ly.gate) * len(pattern_wires(n, ly))
             if ly.source == "WEIGHT":
                 nw = max(nw, ly.offset + k)
             else:
@@ -73,25 +78,44 @@ def param_counts(n, layers):
 
 
 def expand(n, layers):
-    """Gate instances in application order: (gate, wires, source, index, fixed, layer_id)."""
+    """Gate instances in application order:
+    (gate, wires, source, first parameter index, fixed, layer_id, fixed2, fixed3)."""
     out = []
     for li, ly in enumerate(layers):
+        npar = max(1, n_params(ly.gate))
         for k, wires in enumerate(pattern_wires(n, ly)):
             src = ly.source if ly.gate in PARAM_GATES else "FIXED"
-            out.append((ly.gate, tuple(wires), src, ly.offset + k, ly.fixed, li))
+            out.append((ly.gate, tuple(wires), src, ly.offset + npar * k, ly.fixed, li,
+                        getattr(ly, "fixed2", 0.0), getattr(ly, "fixed3", 0.0)))
     return out
 
 
 def instance_param(inst, weights, features):
-    """Scalar (FIXED/WEIGHT) or per-sample vector (INPUT) parameter, or None."""
-    gate, _, src, idx, fixed, _ = inst
+    """The gate's parameter: a scalar (FIXED/WEIGHT) or per-sample vector
+    (INPUT); for Rot a 3-vector, or [B, 3] per sample; None without one."""
+    gate, _, src, idx, fixed = inst[:5]
     if gate not in PARAM_GATES:
         return None
+    if gate == "ROT":
+        if src == "FIXED":
+            return np.array([fixed, inst[6], inst[7]], dtype=np.float64)
+        if src == "WEIGHT":
+            return np.asarray(weights[idx:idx + 3], dtype=np.float64)
+        return np.asarray(features[:, idx:idx + 3], dtype=np.float64)
     if src == "FIXED":
         return float(fixed)
     if src == "WEIGHT":
         return float(weights[idx])
     return np.asarray(features[:, idx], dtype=np.float64)
+
+
+def _per_sample(gate, theta):
+    """Whether a parameter value holds one entry per sample."""
+    return np.ndim(theta) == (2 if gate == "ROT" else 1)
+
+
+def _phases(inst):
+    return (inst[6], inst[7]) if inst[0] == "MS" else (0.0, 0.0)
 
 
 # ---------------------------------------------------------------------------
@@ -153,9 +177,9 @@ def _inst_matrix(inst, theta, B):
     gate = inst[0]
     if theta is None:
         return G.matrix(gate)
-    if np.ndim(theta) == 0:
-        return G.matrix(gate, theta)
-    return np.stack([G.matrix(gate, t) for t in theta])
+    if not _per_sample(gate, theta):
+        return G.matrix(gate, theta, _phases(inst))
+    return np.stack([G.matrix(gate, t, _phases(inst)) for t in theta])
 
 
 def apply_instance(psi, n, inst, theta, adjoint=False):
@@ -218,10 +242,10 @@ def layer_unitary(n, layers, li, weights, x_row):
     U = np.eye(2 ** n, dtype=np.complex128)
     feats = None if x_row is None else np.asarray(x_row)[None, :]
     for inst in expand(n, [layers[li]]):
-        inst = inst[:5] + (li,)
+        inst = inst[:5] + (li,) + inst[6:]
         th = instance_param(inst, weights, feats)
-        if th is not None and np.ndim(th) == 1:
-            th = float(th[0])
+        if th is not None and _per_sample(inst[0], th):
+            th = th[0]
         U = embed_matrix(n, _inst_matrix(inst, th, 1), inst[1]) @ U
     return U
 
@@ -270,23 +294,27 @@ def grad_adjoint(n, layers, weights, features, g):
         th = instance_param(inst, weights, features)
         gate, wires, src = inst[0], inst[1], inst[2]
         if gate in PARAM_GATES and src != "FIXED":
-            if np.ndim(th) == 0:
-                Gm = G.generator(gate, th)
+            if not _per_sample(gate, th):
+                gens = G.generators(gate, th, _phases(inst))
             else:
-                Gm = np.stack([G.generator(gate, t) for t in th])
-            Gpsi = _apply_local(psi, n, Gm, wires)
-            per_b = 2.0 * np.imag(np.sum(np.conj(lam) * Gpsi, axis=1))
-            if src == "WEIGHT":
-                gw[inst[3]] += per_b.sum()
-            else:
-                gx[:, inst[3]] += per_b
+                per = [G.generators(gate, t, _phases(inst)) for t in th]
+                gens = [np.stack([p[k] for p in per]) for k in range(len(per[0]))]
+            for k, Gm in enumerate(gens):
+                Gpsi = _apply_local(psi, n, Gm, wires)
+                per_b = 2.0 * np.imag(np.sum(np.conj(lam) * Gpsi, axis=1))
+                if src == "WEIGHT":
+                    gw[inst[3] + k] += per_b.sum()
+                else:
+                    gx[:, inst[3] + k] += per_b
         psi = apply_instance(psi, n, inst, th, adjoint=True)
         lam = apply_instance(lam, n, inst, th, adjoint=True)
     return e, gw, gx
 
 
+# Rot = P(phi) RY(theta) P(lambda), P(a) = diag(1, e^{ia}) = e^{ia/2} RZ(a):
+# each of its parameters enters as exp(-i a P / 2) up to a global phase
 _SHIFT = {"RX": (np.pi / 2, 0.5), "RY": (np.pi / 2, 0.5), "RZ": (np.pi / 2, 0.5),
-          "ZZ": (np.pi / 2, 0.5), "MS": (0.25, np.pi)}
+          "ZZ": (np.pi / 2, 0.5), "MS": (0.25, np.pi), "ROT": (np.pi / 2, 0.5)}
 
 
 def _per_sample_losses(n, layers, w, x, g):
@@ -306,10 +334,11 @@ def grad_param_shift(n, layers, weights, features, g):
     gx = np.full(features.shape, np.nan)
     kind_w, kind_x = {}, {}
     for inst in expand(n, layers):
-        if inst[2] == "WEIGHT":
-            kind_w.setdefault(inst[3], []).append(inst[0])
-        elif inst[2] == "INPUT":
-            kind_x.setdefault(inst[3], []).append(inst[0])
+        for k in range(n_params(inst[0])):
+            if inst[2] == "WEIGHT":
+                kind_w.setdefault(inst[3] + k, []).append(inst[0])
+            elif inst[2] == "INPUT":
+                kind_x.setdefault(inst[3] + k, []).append(inst[0])
     kind_w = {i: g[0] for i, g in kind_w.items() if len(g) == 1}
     kind_x = {i: g[0] for i, g in kind_x.items() if len(g) == 1}
     for i, gate in kind_w.items():

@@ -166,7 +166,10 @@ __device__ __forceinline__ zd zexpi(double t) {
 enum GateId {
   G_RX = 0, G_RY = 1, G_RZ = 2, G_H = 3, G_X = 4, G_Z = 5, G_S = 6, G_SX = 7, G_GPI = 8, G_GPI2 = 9,
   G_CNOT = 10, G_CZ = 11, G_SWAP = 12, G_ZZ = 13, G_MS = 14, G_ECR = 15,
-  G_GPI_DIAG = 100  // diagonal factor of GPI: diag(e^{2 pi i phi}, e^{-2 pi i phi})
+  G_GPI_DIAG = 100,  // diagonal factor of GPI: diag(e^{2 pi i phi}, e^{-2 pi i phi})
+  G_PHASE = 101,     // diag(1, e^{i t}) (a factor of Rot)
+  G_RZT = 102,       // RZ(2 pi t) (a factor of the H-Rz form of GPI2)
+  G_RZNT = 103       // RZ(-2 pi t)
 };
 
 constexpr double PI = 3.14159265358979323846;
@@ -230,6 +233,20 @@ __device__ void gate2(int g, double t, zd m[4], zd d[4]) {
       d[0] = zmul(zmk(0, 2.0 * PI), e); d[3] = zmul(zmk(0, -2.0 * PI), zconj(e));
       break;
     }
+    case G_PHASE: {
+      zd e = zexpi(t);
+      m[0] = zmk(1, 0); m[3] = e;
+      d[3] = zmul(zmk(0, 1), e);
+      break;
+    }
+    case G_RZT:
+    case G_RZNT: {
+      const double k = g == G_RZT ? PI : -PI;   // RZ(+-2 pi t): phases -+k t
+      zd e = zexpi(k * t);
+      m[0] = zconj(e); m[3] = e;
+      d[0] = zmul(zmk(0, -k), zconj(e)); d[3] = zmul(zmk(0, k), e);
+      break;
+    }
     default:
       m[0] = zmk(1, 0); m[3] = zmk(1, 0);
   }
@@ -279,6 +296,9 @@ __device__ int diag_angles(int g, double t, double a[4], double da[4]) {
     case G_Z: a[1] = PI; return 1;
     case G_S: a[1] = 0.5 * PI; return 1;
     case G_GPI_DIAG: a[0] = 2.0 * PI * t; a[1] = -2.0 * PI * t; da[0] = 2.0 * PI; da[1] = -2.0 * PI; return 1;
+    case G_PHASE: a[1] = t; da[1] = 1.0; return 1;
+    case G_RZT: a[0] = -PI * t; a[1] = PI * t; da[0] = -PI; da[1] = PI; return 1;
+    case G_RZNT: a[0] = PI * t; a[1] = -PI * t; da[0] = PI; da[1] = -PI; return 1;
     case G_ZZ: a[0] = a[3] = -0.5 * t; a[1] = a[2] = 0.5 * t; da[0] = da[3] = -0.5; da[1] = da[2] = 0.5; return 2;
     case G_CZ: a[3] = PI; return 2;
   }
@@ -692,6 +712,9 @@ struct PassArgs {
   // tile is loaded (no separate adjoint-init kernel, no lambda read); g [B, n]
   const double *g;
   int init_lambda;
+  // backward: write the uncomputed psi back (0 when the next backward pass
+  // reads psi from a state stored by the forward pass instead)
+  int store_psi;
 };
 
 template <typename T>
@@ -1399,6 +1422,38 @@ __device__ __forceinline__ void dense_stage(const Ctx<T, K> &c, cplx<T> *Lp, cpl
   if (BWD) dense_apply<T, K, NV, true>(c, Ll, scr, U);
 }
 
+// Hadamard gates on the register bits of MASK as the fast Walsh-Hadamard
+// transform: add / subtract butterflies, then one scale by 2^(-|MASK|/2).
+template <typename T, int MASK>
+__device__ __forceinline__ void wht_apply(cplx<T> (&v)[NREG]) {
+#pragma unroll
+  for (int r = 0; r < RB; ++r) {
+    if (!((MASK >> r) & 1)) continue;
+#pragma unroll
+    for (int j = 0; j < NREG; ++j) {
+      if (j & (1 << r)) continue;
+      const cplx<T> a = v[j], b = v[j | (1 << r)];
+      v[j] = cmk(a.x + b.x, a.y + b.y);
+      v[j | (1 << r)] = cmk(a.x - b.x, a.y - b.y);
+    }
+  }
+  constexpr int k = __builtin_popcount(MASK);
+  const T sc = (k & 1) ? (T)(0.70710678118654752440 / (double)(1 << (k / 2))) : (T)(1.0 / (double)(1 << (k / 2)));
+#pragma unroll
+  for (int j = 0; j < NREG; ++j) v[j] = cmk(v[j].x * sc, v[j].y * sc);
+}
+
+template <typename T>
+__device__ __forceinline__ void wht_dispatch(cplx<T> (&v)[NREG], int mask) {
+  switch (mask) {
+#define X(k) \
+  case k: TQS_CASE_MARK(W##k); wht_apply<T, k>(v); TQS_CASE_MARK(eW##k); break;
+    X(1) X(2) X(3) X(4) X(5) X(6) X(7) X(8) X(9) X(10) X(11) X(12) X(13) X(14) X(15)
+#undef X
+    default: break;
+  }
+}
+
 template <typename T, int K, bool BWD, bool DENSE, bool DIAG>
 __device__ __forceinline__ void run_stage(const Ctx<T, K> &c, const PassArgs<T> &a, const UStage &S, cplx<T> *Lp,
                           cplx<T> *Ll, const cplx<T> *tab, bool grad_only) {
@@ -1517,6 +1572,10 @@ __device__ __forceinline__ void run_stage(const Ctx<T, K> &c, const PassArgs<T> 
         for (int q = 0; q < 4; ++q) m[r][q] = kld(ms, q);
       }
       u1g_run<T, K, BWD>(c, a, vp, vl, m, ga, op.r0);
+    } else if (op.kind == OP_WHT) {
+      // H is its own inverse and has no parameter
+      wht_dispatch<T>(vp, op.r0);
+      if (BWD) wht_dispatch<T>(vl, op.r0);
     } else if (op.kind == OP_SEQ) {
       seq_run<T, K, BWD>(c, a, vp, vl, a.seqs + op.aux, op.r0, op.sub);
     } else if (op.kind == OP_U2G) {
@@ -1966,8 +2025,10 @@ __attribute__((amdgpu_waves_per_eu(PassOcc<T, BWD, DENSE>::waves))) k_pass(PassA
       }
     }
     cplx<T> *d0 = a.dst0 + (long long)c.sample0 * sstride;
+    if (!BWD || uni(a.store_psi)) {
 #pragma unroll
-    for (int i = 0; i < NREG; ++i) d0[kk[i]] = tp[i];
+      for (int i = 0; i < NREG; ++i) d0[kk[i]] = tp[i];
+    }
     if (BWD) {
       cplx<T> *d1 = a.dst1 + (long long)c.sample0 * sstride;
 #pragma unroll
@@ -1981,7 +2042,7 @@ __attribute__((amdgpu_waves_per_eu(PassOcc<T, BWD, DENSE>::waves))) k_pass(PassA
       const int j = t & ((1 << c.nv) - 1);
       if (smp < a.batch && j < (1 << n)) {
         const long long g = (long long)smp * sstride + j;
-        a.dst0[g] = tp[i];
+        if (!BWD || a.store_psi) a.dst0[g] = tp[i];
         if (BWD) a.dst1[g] = tl[i];
       }
     }

@@ -38,6 +38,8 @@ enum OpKind : int32_t {
                  // aux = DevGroup index (the gates act on distinct bits, so they commute)
   OP_U2G = 9,    // two structured 4x4 gates of one kind (sub) on disjoint register-bit
                  // pairs: r0 = a<<6 | b<<4 | c<<2 | d for pairs (a,b), (c,d); aux = DevGroup
+  OP_WHT = 11,   // Hadamard gates on the register bits of mask r0, applied as the
+                 // fast Walsh-Hadamard transform: add / subtract butterflies, one scale
   OP_SEQ = 10,   // the brick-layer stage program, one op: pair gates of kind `sub` on
                  // register pairs (0,1),(2,3); 2x2 gates on bits 0-3; then (r0 >= 3) a pair
                  // gate on (1,2); then (r0 == 4) 2x2 gates on bits 1, 2.  r0 = program
@@ -49,6 +51,7 @@ enum OpFlag : int32_t {
   F_PERSAMPLE = 2,   // matrix / angles differ per sample
   F_GRAD = 4,        // op carries gradient accumulators
   F_DIAGONAL = 8,    // U1/U2 matrix is diagonal
+  F_HADAMARD = 16,   // U1 matrix is the Hadamard gate (no parameter)
 };
 
 // Structure of a 4x4 op, chosen by the planner from the gate.

@@ -37,13 +37,21 @@ constexpr int DENSE_MAX_QUBITS = 6;
 constexpr int DENSE_AUTO_MAX_QUBITS = 0;
 
 // gate ids (tqs_gate)
-enum { RX = 0, RY, RZ, H, X, Z, S, SX, GPI, GPI2, CNOT, CZ, SWAP, ZZ, MS, ECR, GPI_DIAG = 100 };
+// gates a layer may name (tqs_gate), then factors the planner makes of them:
+// GPI_DIAG diag(e^{2 pi i p}, e^{-2 pi i p}); PHASE diag(1, e^{ip}); RZT = RZ(2 pi p);
+// RZNT = RZ(-2 pi p)
+enum { RX = 0, RY, RZ, H, X, Z, S, SX, GPI, GPI2, CNOT, CZ, SWAP, ZZ, MS, ECR, ROT,
+       GPI_DIAG = 100, PHASE = 101, RZT = 102, RZNT = 103 };
 enum { PAT_ALL = 0, PAT_WIRE, PAT_RING, PAT_CHAIN, PAT_PEVEN, PAT_PODD };
 enum { SRC_FIXED = 0, SRC_WEIGHT, SRC_INPUT };
 
-static bool is_1q(int g) { return g >= RX && g <= GPI2; }
-static bool is_param(int g) { return g == RX || g == RY || g == RZ || g == GPI || g == GPI2 || g == ZZ || g == MS || g == GPI_DIAG; }
-static bool is_diag1(int g) { return g == RZ || g == Z || g == S || g == GPI_DIAG; }
+static bool is_1q(int g) { return (g >= RX && g <= GPI2) || g == ROT || g == PHASE || g == RZT || g == RZNT; }
+static bool is_param(int g) {
+  return g == RX || g == RY || g == RZ || g == GPI || g == GPI2 || g == ZZ || g == MS || g == ROT || g == GPI_DIAG ||
+         g == PHASE || g == RZT || g == RZNT;
+}
+static bool is_diag1(int g) { return g == RZ || g == Z || g == S || g == GPI_DIAG || g == PHASE || g == RZT || g == RZNT; }
+static int gate_params(int g) { return g == ROT ? 3 : (is_param(g) ? 1 : 0); }
 static bool is_diag2(int g) { return g == ZZ || g == CZ; }
 static bool is_real_gate(int g) { return g == RY || g == H || g == X || g == Z || g == CNOT || g == SWAP || g == CZ; }
 static int popc(uint32_t x) { return __builtin_popcount(x); }
@@ -152,7 +160,7 @@ std::string validate_layers(int n, const LayerSpec *layers, int n_layers, int *n
   int w = 0, f = 0;
   for (int li = 0; li < n_layers; ++li) {
     const LayerSpec &L = layers[li];
-    if (L.gate < RX || L.gate > ECR) {
+    if (L.gate < RX || L.gate > ROT) {
       snprintf(buf, sizeof buf, "EINVAL: layer %d: unknown gate %d", li, L.gate);
       return buf;
     }
@@ -199,8 +207,14 @@ std::string validate_layers(int n, const LayerSpec *layers, int n_layers, int *n
         snprintf(buf, sizeof buf, "EINVAL: layer %d: negative offset", li);
         return buf;
       }
-      if (L.source == SRC_WEIGHT) w = std::max(w, L.offset + count);
-      else f = std::max(f, L.offset + count);
+      // int64: an offset near INT32_MAX must not wrap the parameter count
+      const long long end = (long long)L.offset + (long long)gate_params(L.gate) * count;
+      if (end > INT32_MAX) {
+        snprintf(buf, sizeof buf, "EINVAL: layer %d: offset + parameter count exceeds INT32_MAX", li);
+        return buf;
+      }
+      if (L.source == SRC_WEIGHT) w = std::max(w, (int)end);
+      else f = std::max(f, (int)end);
     }
   }
   if (nw) *nw = w;
@@ -208,20 +222,81 @@ std::string validate_layers(int n, const LayerSpec *layers, int n_layers, int *n
   return "";
 }
 
-static std::vector<Inst> expand(int n, const LayerSpec *layers, int n_layers) {
+// One gate of a sub-layer, before placement on wires: gate, source, parameter
+// offset relative to the gate's first parameter, fixed value.
+struct SubGate {
+  int gate, src, poff;
+  double fixed;
+};
+
+// The sub-layers one 1-qubit gate becomes (application order).  Rot(theta,
+// phi, lambda) = P(phi) RY(theta) P(lambda) (Appendix A, P = diag(1, e^{ia})).
+// With the H-Rz expansion (Sec. 2.5): RX = H RZ H; RY = S H RZ H S^dag;
+// GPI2(phi) = RZ(2 pi phi) RX(pi/2) RZ(-2 pi phi), RX(pi/2) = H RZ(pi/2) H.
+static std::vector<SubGate> sub_gates_1q(int g, int src, double fixed, double f2, double f3, bool hrz) {
+  const double hp = 1.5707963267948966;
+  auto ry = [&](int s, int off, double fx) -> std::vector<SubGate> {
+    if (!hrz) return {{RY, s, off, fx}};
+    return {{PHASE, SRC_FIXED, 0, -hp}, {H, SRC_FIXED, 0, 0.0}, {RZ, s, off, fx}, {H, SRC_FIXED, 0, 0.0},
+            {PHASE, SRC_FIXED, 0, hp}};
+  };
+  if (g == ROT) {
+    std::vector<SubGate> v = {{PHASE, src, 2, f3}};
+    for (const SubGate &x : ry(src, 0, fixed)) v.push_back(x);
+    v.push_back({PHASE, src, 1, f2});
+    return v;
+  }
+  if (hrz && g == RX) return {{H, SRC_FIXED, 0, 0.0}, {RZ, src, 0, fixed}, {H, SRC_FIXED, 0, 0.0}};
+  if (hrz && g == RY) return ry(src, 0, fixed);
+  if (hrz && g == GPI2)
+    return {{RZNT, src, 0, fixed}, {H, SRC_FIXED, 0, 0.0}, {RZ, SRC_FIXED, 0, hp}, {H, SRC_FIXED, 0, 0.0},
+            {RZT, src, 0, fixed}};
+  return {{g, src, 0, fixed}};
+}
+
+// Gate instances in application order.  A layer whose gates become several
+// factors is emitted as consecutive sub-layers (all wires' first factors,
+// then all second factors, ...): factors on different wires commute, so this
+// is the same product, and the per-layer dispatcher sees uniform layers.
+static std::vector<Inst> expand(int n, const LayerSpec *layers, int n_layers, bool hrz) {
+  constexpr int SUBS = 16;   // sub-layer slots per layer
   std::vector<Inst> out;
   for (int li = 0; li < n_layers; ++li) {
     const LayerSpec &L = layers[li];
     const int src = is_param(L.gate) ? L.source : SRC_FIXED;
+    const int np = std::max(1, gate_params(L.gate));
     if (is_1q(L.gate)) {
+      const std::vector<SubGate> sg = sub_gates_1q(L.gate, src, L.fixed, L.fixed2, L.fixed3, hrz);
+      std::vector<int> wires;
       if (L.pattern == PAT_ALL)
-        for (int q = 0; q < n; ++q) out.push_back({L.gate, q, -1, src, L.offset + q, li, L.fixed});
+        for (int q = 0; q < n; ++q) wires.push_back(q);
       else
-        out.push_back({L.gate, L.wire, -1, src, L.offset, li, L.fixed});
+        wires.push_back(L.wire);
+      for (size_t k = 0; k < sg.size(); ++k)
+        for (size_t i = 0; i < wires.size(); ++i) {
+          const int first = L.offset + np * (L.pattern == PAT_ALL ? wires[i] : 0);
+          const SubGate &x = sg[k];
+          out.push_back({x.gate, wires[i], -1, x.src, x.src == SRC_FIXED ? 0 : first + x.poff,
+                         li * SUBS + (int)k, x.fixed});
+        }
     } else {
       const auto pr = pattern_pairs(n, L);
+      // MS(phi0, phi1, theta) = (D1 (x) D0) MS(theta) (D1 (x) D0)^dag with
+      // D = RZ(2 pi phi) (P(phi) = D X D^dag, Appendix A as read)
+      const bool phased = L.gate == MS && (L.fixed2 != 0.0 || L.fixed3 != 0.0);
+      const double tp = 6.283185307179586;
+      if (phased)
+        for (size_t k = 0; k < pr.size(); ++k) {
+          out.push_back({RZ, pr[k].first, -1, SRC_FIXED, 0, li * SUBS, -tp * L.fixed3});
+          out.push_back({RZ, pr[k].second, -1, SRC_FIXED, 0, li * SUBS, -tp * L.fixed2});
+        }
       for (size_t k = 0; k < pr.size(); ++k)
-        out.push_back({L.gate, pr[k].first, pr[k].second, src, L.offset + (int)k, li, L.fixed});
+        out.push_back({L.gate, pr[k].first, pr[k].second, src, L.offset + (int)k, li * SUBS + 1, L.fixed});
+      if (phased)
+        for (size_t k = 0; k < pr.size(); ++k) {
+          out.push_back({RZ, pr[k].first, -1, SRC_FIXED, 0, li * SUBS + 2, tp * L.fixed3});
+          out.push_back({RZ, pr[k].second, -1, SRC_FIXED, 0, li * SUBS + 2, tp * L.fixed2});
+        }
     }
   }
   return out;
@@ -491,10 +566,12 @@ static std::string build_ir(Plan &P, const std::vector<Inst> &insts) {
   for (auto &op : P.ops) finish_op(P, op);
   // single-sample-per-workgroup tiles cannot hold per-sample diagonal tables when
   // several samples share a workgroup: turn such terms into 1q / 2q ops
-  if (multi) {
+  // and with the diagonal-Einsum technique every diagonal layer is applied
+  // gate by gate, one diagonal factor per gate (Sec. 2.4.3)
+  if (multi || P.opts.diag == 1) {
     std::vector<IrOp> out;
     for (auto &op : P.ops) {
-      if (op.kind == IR_DIAG && op.per_sample) {
+      if (op.kind == IR_DIAG && (op.per_sample || P.opts.diag == 1)) {
         for (const IrTerm &t : op.terms) {
           IrOp o;
           o.kind = t.nbits == 1 ? IR_U1 : IR_U2;
@@ -626,6 +703,33 @@ struct Sched {
 };
 
 }  // namespace
+
+// Runs of consecutive Hadamard ops on distinct register bits of one stage
+// become one OP_WHT op (the fast Walsh-Hadamard transform over those bits).
+static void group_wht(Plan &P, int begin) {
+  std::vector<DevOp> out;
+  size_t i = begin;
+  while (i < P.dop.size()) {
+    if (!(P.dop[i].kind == OP_U1 && (P.dop[i].flags & F_HADAMARD))) {
+      out.push_back(P.dop[i++]);
+      continue;
+    }
+    int mask = 0;
+    size_t j = i;
+    while (j < P.dop.size() && P.dop[j].kind == OP_U1 && (P.dop[j].flags & F_HADAMARD) &&
+           !(mask & (1 << P.dop[j].r0)))
+      mask |= 1 << P.dop[j++].r0;
+    DevOp o;
+    std::memset(&o, 0, sizeof o);
+    o.kind = OP_WHT;
+    o.r0 = mask;
+    o.acc = -1;
+    out.push_back(o);
+    i = j;
+  }
+  P.dop.resize(begin);
+  P.dop.insert(P.dop.end(), out.begin(), out.end());
+}
 
 // Runs of consecutive complex single-qubit ops (shared matrices) on distinct
 // register bits of one stage become one OP_U1G op: they commute, so the kernel
@@ -1170,6 +1274,7 @@ static std::string emit(Plan &P) {
         o.r0 = ridx(tix.at(op.bits[0]));
         o.mat = op_mat[oi_ir];
         o.flags = (op.real ? F_REAL : 0) | (op.per_sample ? F_PERSAMPLE : 0) | (op.diagonal ? F_DIAGONAL : 0);
+        if (P.opts.fhwt && op.factors.size() == 1 && P.factors[op.factors[0]].gate == H) o.flags |= F_HADAMARD;
         if (op.has_grad) {
           o.flags |= F_GRAD;
           o.acc = n_acc;
@@ -1396,6 +1501,7 @@ static std::string emit(Plan &P) {
       for (int k = 0; k < RB; ++k) st.rbits[k] = S[k];
       for (int j : stage_ops) emit_op(P.ops[po[j]], po[j], S);
       if (!emit_error.empty()) return emit_error;
+      group_wht(P, st.op_begin);
       group_u1(P, st.op_begin);
       group_u2(P, st.op_begin);
       group_seq(P, st.op_begin);
@@ -1512,10 +1618,12 @@ static std::string emit(Plan &P) {
   return "";
 }
 
-std::string build_plan(Plan &P, int n, const LayerSpec *layers, int n_layers, int dtype, int mode,
-                       int tile_bits) {
+std::string build_plan(Plan &P, int n, const LayerSpec *layers, int n_layers, int dtype,
+                       const PlanOptions &opts) {
   std::string err = validate_layers(n, layers, n_layers, &P.n_weights, &P.n_features);
   if (!err.empty()) return err;
+  P.opts = opts;
+  const int mode = opts.mode, tile_bits = opts.tile_bits;
   P.n = n;
   P.nv = std::max(n, RB);
   P.dtype = dtype;
@@ -1533,7 +1641,7 @@ std::string build_plan(Plan &P, int n, const LayerSpec *layers, int n_layers, in
   P.dense = want_dense && P.resident && P.nv <= DENSE_MAX_QUBITS && K - P.nv >= 4;
   P.factors.clear();
   P.ops.clear();
-  std::vector<Inst> insts = expand(n, layers, n_layers);
+  std::vector<Inst> insts = expand(n, layers, n_layers, opts.hrz != 0);
   err = build_ir(P, insts);
   if (!err.empty()) return err;
   err = schedule(P, K);
@@ -1565,7 +1673,12 @@ void pass_flops(const Plan &P, int pass, double *fwd, double *bwd) {
     const IrOp &op = P.ops[oi];
     double of = 0.0;
     switch (op.kind) {
-      case IR_U1: of = op.diagonal ? 6.0 : (op.real ? 8.0 : 16.0); break;
+      case IR_U1:
+        if (P.opts.fhwt && op.factors.size() == 1 && P.factors[op.factors[0]].gate == H)
+          of = 2.0;   // a complex add or subtract per amplitude (the scale is shared)
+        else
+          of = op.diagonal ? 6.0 : (op.real ? 8.0 : 16.0);
+        break;
       case IR_U2: {
         const int gt = op.factors.empty() ? -1 : P.factors[op.factors[0]].gate;
         if (gt == CNOT || gt == SWAP) of = 0.0;
@@ -1596,11 +1709,12 @@ std::string describe_plan(const Plan &P) {
   o << "{\"n\":" << P.n << ",\"dtype\":\"" << (P.dtype ? "c128" : "c64") << "\",\"mode\":\""
     << (P.dense ? "dense" : (P.mode == 1 ? "per_layer" : "fused")) << "\",\"resident\":" << (P.resident ? "true" : "false")
     << ",\"n_weights\":" << P.n_weights << ",\"n_features\":" << P.n_features << ",\"n_ops\":" << P.ops.size()
-    << ",\"n_acc\":" << P.n_acc << ",\"passes\":[";
+    << ",\"n_acc\":" << P.n_acc << ",\"hrz\":" << P.opts.hrz << ",\"fhwt\":" << P.opts.fhwt
+    << ",\"diag\":\"" << (P.opts.diag ? "einsum" : "tables") << "\",\"passes\":[";
   for (size_t p = 0; p < P.passes.size(); ++p) {
     const PlanPass &pp = P.passes[p];
     const DevPass &d = P.dpass[p];
-    int nu1 = 0, nu2 = 0, ndg = 0, npm = 0, ndense = 0, ngrp = 0;
+    int nu1 = 0, nu2 = 0, ndg = 0, npm = 0, ndense = 0, ngrp = 0, nwht = 0;
     for (int s = d.stage_begin; s < d.stage_begin + d.n_stages; ++s)
       for (int oi = P.dstage[s].op_begin; oi < P.dstage[s].op_end; ++oi) {
         const int k = P.dop[oi].kind;
@@ -1616,6 +1730,7 @@ std::string describe_plan(const Plan &P) {
           ++ngrp;
         }
         nu2 += (k == OP_U2) + 2 * (k == OP_U2G);
+        if (k == OP_WHT) nwht += __builtin_popcount((unsigned)P.dop[oi].r0);
         ndg += k == OP_DIAG;
         npm += k == OP_PERM;
         ndense += k == OP_DENSE;
@@ -1626,7 +1741,7 @@ std::string describe_plan(const Plan &P) {
       << "\",\"store\":\"" << (pp.has_store ? "scatter" : "tile") << "\",\"bwd_only\":"
       << (pp.bwd_only ? "true" : "false") << ",\"stages\":" << d.n_stages << ",\"u1\":" << nu1
       << ",\"u1_groups\":" << ngrp << ",\"u2\":" << nu2 << ",\"diag\":" << ndg << ",\"perm\":" << npm
-      << ",\"dense\":" << ndense
+      << ",\"dense\":" << ndense << ",\"wht\":" << nwht
       << ",\"grad_wires\":"
       << pp.grad_wires.size() << ",\"outside_wires\":" << pp.outside_wires.size() << ",\"n_acc\":" << d.n_acc;
     double ff = 0, fb = 0;

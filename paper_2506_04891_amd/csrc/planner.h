@@ -41,6 +41,21 @@ struct IrOp {
   bool has_grad = false;
 };
 
+struct LayerSpec {
+  int gate, pattern, source, wire, wire2, offset;
+  double fixed, fixed2, fixed3;   // fixed2/3: MS phases (phi0, phi1); FIXED Rot's phi, lambda
+};
+
+// Dispatcher choices that change the plan.
+struct PlanOptions {
+  int mode = 0;          // 0 auto, 1 per-layer passes, 2 fused passes, 3 dense
+  int tile_bits = 0;     // 0 auto, else K
+  int hrz = 0;           // 1: H-Rz expansion of RX, RY, GPI2 and Rot layers (Sec. 2.5)
+  int fhwt = 1;          // 1: Hadamard layers as add/subtract butterflies (fast Walsh-Hadamard)
+  int diag = 0;          // 0: diagonal layers by split eigenphase tables (Secs. 2.4.1-2.4.2);
+                         // 1: gate by gate, one diagonal factor per gate (diagonal Einsum, Sec. 2.4.3)
+};
+
 struct PlanPass {
   int K = 12;
   std::vector<int> tile;           // tile bits -> state bits (ascending)
@@ -56,6 +71,7 @@ struct PlanPass {
 struct Plan {
   // configuration
   int n = 0, nv = 0, dtype = 0, mode = 0, tile_bits = 0;
+  PlanOptions opts;
   bool dense = false;                    // weight-only layers applied as full unitaries (MFMA)
   int n_weights = 0, n_features = 0;
   bool resident = false;
@@ -92,19 +108,14 @@ struct Plan {
   int first_fwd_writes_x = 0;            // first forward pass writes the workspace buffer
 };
 
-struct LayerSpec {
-  int gate, pattern, source, wire, wire2, offset;
-  double fixed;
-};
-
 // Validates the layer list (returns a message starting with "EINVAL:" or
 // "EUNSUPPORTED:" on failure) and fills n_weights / n_features.
 std::string validate_layers(int n, const LayerSpec *layers, int n_layers, int *n_weights,
                             int *n_features);
 
 // Builds the plan; returns an empty string on success or an error message.
-std::string build_plan(Plan &P, int n, const LayerSpec *layers, int n_layers, int dtype, int mode,
-                       int tile_bits);
+std::string build_plan(Plan &P, int n, const LayerSpec *layers, int n_layers, int dtype,
+                       const PlanOptions &opts);
 
 std::string describe_plan(const Plan &P);
 

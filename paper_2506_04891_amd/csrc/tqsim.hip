@@ -55,7 +55,15 @@ struct tqs_circuit {
   std::vector<std::string> kind_names;
   std::vector<ProfAgg> agg;
   std::vector<LayerSpec> layers;
-  int n = 0, dtype = 0, mode = 0, tile_bits = 0;
+  int n = 0, dtype = 0;
+  PlanOptions opts;
+  // backward: 0 = adjoint with uncompute (psi rebuilt pass by pass with the
+  // inverse layers), 1 = stored states (every forward pass keeps its output;
+  // the backward reads psi from there and writes only lambda), 2 = stored when
+  // the stored states fit stored_cap bytes and the plan has at most
+  // STORED_AUTO_MAX_PASSES forward passes, adjoint otherwise
+  int backward = 0;
+  long long stored_cap = 8ll << 30;
   std::mutex mu;
   bool uploaded = false;
   int device = -1;
@@ -151,26 +159,56 @@ tqs_status upload(tqs_circuit *c) {
 }
 
 struct WsLayout {
-  size_t x = 0, la = 0, lb = 0, mats = 0, mats_ps = 0, dbl = 0, dbl_ps = 0, dtab = 0, partials = 0, A = 0, ev = 0;
-  size_t total = 0;
-  bool has_x = false, has_lb = false;
+  size_t x = 0, la = 0, lb = 0, st = 0, mats = 0, mats_ps = 0, dbl = 0, dbl_ps = 0, dtab = 0, partials = 0, A = 0,
+         ev = 0;
+  size_t total = 0, state = 0;
+  bool has_x = false, has_lb = false, stored = false;
+  int n_stored = 0;   // forward pass outputs kept in the workspace (all but the last)
 };
 
 size_t expval_partials_bytes(const Plan &P, int B);
 
-WsLayout layout(const Plan &P, int B, bool grad) {
+int forward_passes(const Plan &P) {
+  int m = 0;
+  for (const PlanPass &pp : P.passes) m += !pp.bwd_only;
+  return m;
+}
+
+// Stored-state backward with more forward passes than this is not chosen
+// automatically (option backward = 2).
+constexpr int STORED_AUTO_MAX_PASSES = 64;
+
+// Whether the stored-state backward serves batch B: the workspace layout of
+// forward and backward calls depends on it, and both derive it from (plan, B).
+bool use_stored(const tqs_circuit *c, int B) {
+  if (c->backward == 1) return true;
+  if (c->backward != 2) return false;
+  const Plan &P = c->plan;
+  const int m = forward_passes(P);
+  const double bytes = (double)(m - 1) * (double)((size_t)B << P.n) * (P.dtype ? 16.0 : 8.0);
+  return m <= STORED_AUTO_MAX_PASSES && bytes <= (double)c->stored_cap;
+}
+
+WsLayout layout(const Plan &P, int B, bool grad, bool stored) {
   WsLayout L;
   const size_t es = P.dtype ? 16 : 8;
   const size_t state = ((size_t)B << P.n) * es;
+  L.state = state;
   size_t off = 0;
   auto take = [&](size_t bytes) {
     const size_t o = off;
     off += align256(bytes ? bytes : 1);
     return o;
   };
+  L.stored = stored;
   L.has_x = P.any_oop;
   L.has_lb = grad && P.any_oop;
   if (L.has_x) L.x = take(state);
+  if (stored) {
+    // outputs of forward passes 0 .. m-2 (the last pass writes the caller's state)
+    L.n_stored = std::max(0, forward_passes(P) - 1);
+    L.st = take(state * (size_t)L.n_stored);
+  }
   if (grad) L.la = take(state);
   if (L.has_lb) L.lb = take(state);
   L.mats = take((size_t)P.n_mats * es);
@@ -187,10 +225,12 @@ WsLayout layout(const Plan &P, int B, bool grad) {
   return L;
 }
 
-int pass_grid(const DevPass &d, int B) {
-  if (d.nv >= d.K) return B << (d.nv - d.K);
-  const int spw = 1 << (d.K - d.nv);
-  return (B + spw - 1) / spw;
+// Workgroups of one pass launch, in 64-bit arithmetic (B near INT32_MAX with
+// several samples per workgroup must not wrap).
+long long pass_grid(const DevPass &d, int B) {
+  if (d.nv >= d.K) return (long long)B << (d.nv - d.K);
+  const long long spw = 1ll << (d.K - d.nv);
+  return ((long long)B + spw - 1) / spw;
 }
 
 int prof_kind(tqs_circuit *c, const std::string &name) {
@@ -245,7 +285,7 @@ struct ProfScope {
 template <typename T, bool BWD>
 tqs_status launch_pass(tqs_circuit *c, int pi, int B, const cplx<T> *src0, cplx<T> *dst0,
                        const cplx<T> *src1, cplx<T> *dst1, char *ws, const WsLayout &L,
-                       hipStream_t s, const double *g_init = nullptr) {
+                       hipStream_t s, const double *g_init = nullptr, bool store_psi = true) {
   const Plan &P = c->plan;
   const DevPass &d = P.dpass[pi];
   PassArgs<T> a;
@@ -275,14 +315,17 @@ tqs_status launch_pass(tqs_circuit *c, int pi, int B, const cplx<T> *src0, cplx<
   a.batch = B;
   a.g = g_init;
   a.init_lambda = g_init != nullptr;
-  const int grid = pass_grid(d, B);
+  a.store_psi = store_psi ? 1 : 0;
+  const long long grid_ll = pass_grid(d, B);
+  if (grid_ll > INT32_MAX) return fail(TQS_EINVAL, "batch too large: pass grid exceeds 2^31 - 1 workgroups");
+  const int grid = (int)grid_ll;
   const size_t es = sizeof(cplx<T>);
   const size_t lds = ((size_t)(BWD ? 2 : 1) * ((size_t)1 << d.K) + (size_t)d.diag_lds) * es;
   double bytes = 0, flops = 0;
   if (c->profile) {
     const double amps = (double)B * (double)(1ll << P.n);
     if (BWD)
-      bytes = amps * es * ((g_init ? 1.0 : 2.0) + (d.skip_bwd_store ? 0.0 : 2.0));
+      bytes = amps * es * ((g_init ? 1.0 : 2.0) + (d.skip_bwd_store ? 0.0 : (store_psi ? 2.0 : 1.0)));
     else
       bytes = amps * es * ((d.load_mode == LOAD_GLOBAL ? 1.0 : 0.0) + 1.0);
     double ff = 0, fb = 0;
@@ -358,6 +401,19 @@ tqs_status forward_t(tqs_circuit *c, int B, const double *w, const double *x, vo
     if (P.passes[fwd[i]].has_load || P.passes[fwd[i]].has_store) ++k;
   cplx<T> *S = reinterpret_cast<cplx<T> *>(state);
   cplx<T> *X = L.has_x ? reinterpret_cast<cplx<T> *>(ws + L.x) : nullptr;
+  if (L.stored) {
+    // every pass out of place into its own buffer; the last into the caller's
+    cplx<T> *ST = reinterpret_cast<cplx<T> *>(ws + L.st);
+    const size_t elems = (size_t)B << P.n;
+    cplx<T> *prev = nullptr;
+    for (size_t i = 0; i < fwd.size(); ++i) {
+      cplx<T> *dst = (i + 1 == fwd.size()) ? S : ST + i * elems;
+      st = launch_pass<T, false>(c, fwd[i], B, i == 0 ? dst : prev, dst, nullptr, nullptr, ws, L, s);
+      if (st != TQS_OK) return st;
+      prev = dst;
+    }
+    return TQS_OK;
+  }
   cplx<T> *cur = (k % 2 == 0) ? S : X;
   for (size_t i = 0; i < fwd.size(); ++i) {
     const PlanPass &pp = P.passes[fwd[i]];
@@ -444,6 +500,30 @@ tqs_status adjoint_t(tqs_circuit *c, int B, const double *w, const double *x, vo
     ps.end();
     HIP_TRY(hipGetLastError());
   }
+  if (L.stored) {
+    // psi of each forward pass comes from its stored output; only lambda is
+    // written back, except where a gradient-only pass needs the uncomputed psi
+    cplx<T> *ST = reinterpret_cast<cplx<T> *>(ws + L.st);
+    const size_t elems = (size_t)B << P.n;
+    std::vector<int> fidx(P.passes.size(), -1);
+    int m = 0;
+    for (size_t p = 0; p < P.passes.size(); ++p)
+      if (!P.passes[p].bwd_only) fidx[p] = m++;
+    cplx<T> *pc = nullptr, *lc = LA;
+    for (int p = (int)P.passes.size() - 1; p >= 0; --p) {
+      const PlanPass &pp = P.passes[p];
+      const bool oop = pp.has_load || pp.has_store;
+      cplx<T> *psrc = pp.bwd_only ? pc : (fidx[p] == m - 1 ? S : ST + (size_t)fidx[p] * elems);
+      const bool store = pp.bwd_only || (p > 0 && P.passes[p - 1].bwd_only);
+      cplx<T> *pdst = (store && oop) ? (psrc == X ? S : X) : psrc;
+      cplx<T> *ld = oop ? ((lc == LA) ? LB : LA) : lc;
+      st = launch_pass<T, true>(c, p, B, psrc, pdst, lc, ld, ws, L, s, (fused_init && p == last) ? g : nullptr,
+                                store);
+      if (st != TQS_OK) return st;
+      pc = pdst;
+      lc = ld;
+    }
+  } else {
   cplx<T> *pc = S, *lc = LA;
   for (int p = (int)P.passes.size() - 1; p >= 0; --p) {
     const PlanPass &pp = P.passes[p];
@@ -457,6 +537,7 @@ tqs_status adjoint_t(tqs_circuit *c, int B, const double *w, const double *x, vo
     if (st != TQS_OK) return st;
     pc = pd;
     lc = ld;
+  }
   }
   double *A = reinterpret_cast<double *>(ws + L.A);
   ProfScope psf(c, s, "grad_finalize", 0.0, 0.0);
@@ -495,13 +576,14 @@ tqs_status check_batch(const tqs_circuit *c, int B) {
   if (c->n + es_log + 31 - __builtin_clz((unsigned)B) >= 62)
     return fail(TQS_EINVAL, "batch * 2^n * element size overflows int64");
   if ((long long)B * (1ll << c->plan.nv) > (1ll << 40)) return fail(TQS_EINVAL, "state too large");
+  for (const DevPass &d : c->plan.dpass)
+    if (pass_grid(d, B) > INT32_MAX) return fail(TQS_EINVAL, "batch too large: a pass grid exceeds 2^31 - 1");
   return TQS_OK;
 }
 
 tqs_status rebuild(tqs_circuit *c) {
   Plan P;
-  std::string e = build_plan(P, c->n, c->layers.data(), (int)c->layers.size(), c->dtype, c->mode,
-                             c->tile_bits);
+  std::string e = build_plan(P, c->n, c->layers.data(), (int)c->layers.size(), c->dtype, c->opts);
   if (!e.empty()) return from_msg(e);
   c->plan = std::move(P);
   return TQS_OK;
@@ -530,6 +612,8 @@ tqs_status tqs_circuit_create(int32_t n_qubits, const tqs_layer *layers, int32_t
     L.wire2 = layers[i].wire2;
     L.offset = layers[i].offset;
     L.fixed = layers[i].fixed_param;
+    L.fixed2 = layers[i].fixed_param2;
+    L.fixed3 = layers[i].fixed_param3;
     c->layers.push_back(L);
   }
   tqs_status st = rebuild(c);
@@ -573,7 +657,7 @@ tqs_status tqs_workspace_size(const tqs_circuit *c, int32_t batch, int32_t with_
   tqs_status st = check_batch(c, batch);
   if (st != TQS_OK) return st;
   if (!bytes) return fail(TQS_EINVAL, "bytes is NULL");
-  *bytes = layout(c->plan, batch, with_grad != 0).total;
+  *bytes = layout(c->plan, batch, with_grad != 0, use_stored(c, batch)).total;
   return TQS_OK;
 }
 
@@ -584,7 +668,7 @@ tqs_status tqs_forward(tqs_circuit *c, int32_t batch, const double *weights_d, c
   if (!state_d || !ws_d) return fail(TQS_EINVAL, "state or workspace is NULL");
   if (c->plan.n_weights > 0 && !weights_d) return fail(TQS_EINVAL, "weights are NULL");
   if (c->plan.n_features > 0 && !features_d) return fail(TQS_EINVAL, "features are NULL");
-  const WsLayout L = layout(c->plan, batch, false);
+  const WsLayout L = layout(c->plan, batch, false, use_stored(c, batch));
   if (ws_bytes < L.total) return fail(TQS_ENOMEM, "workspace too small");
   st = upload(c);
   if (st != TQS_OK) return st;
@@ -599,7 +683,7 @@ tqs_status tqs_expval_z(const tqs_circuit *c, int32_t batch, const void *state_d
   tqs_status st = check_batch(c, batch);
   if (st != TQS_OK) return st;
   if (!state_d || !expz_d || !ws_d) return fail(TQS_EINVAL, "state, expz or workspace is NULL");
-  const WsLayout L = layout(c->plan, batch, false);
+  const WsLayout L = layout(c->plan, batch, false, use_stored(c, batch));
   if (ws_bytes < L.total) return fail(TQS_ENOMEM, "workspace too small");
   char *ws = static_cast<char *>(ws_d);
   double *part = reinterpret_cast<double *>(ws + L.ev);
@@ -616,7 +700,7 @@ tqs_status tqs_adjoint_grad(tqs_circuit *c, int32_t batch, const double *weights
   if (c->plan.n_weights > 0 && (!weights_d || !grad_weights_d))
     return fail(TQS_EINVAL, "weights or weight gradients are NULL");
   if (c->plan.n_features > 0 && !features_d) return fail(TQS_EINVAL, "features are NULL");
-  const WsLayout L = layout(c->plan, batch, true);
+  const WsLayout L = layout(c->plan, batch, true, use_stored(c, batch));
   if (ws_bytes < L.total) return fail(TQS_ENOMEM, "workspace too small");
   st = upload(c);
   if (st != TQS_OK) return st;
@@ -639,10 +723,21 @@ tqs_status tqs_set_option(tqs_circuit *c, const char *key, int64_t value) {
   }
   if (std::strcmp(key, "mode") == 0) {
     if (value < 0 || value > 3) return fail(TQS_EINVAL, "mode must be 0..3");
-    c->mode = (int)value;
+    c->opts.mode = (int)value;
+  } else if (std::strcmp(key, "hrz") == 0 || std::strcmp(key, "fhwt") == 0 || std::strcmp(key, "diag") == 0) {
+    if (value < 0 || value > 1) return fail(TQS_EINVAL, std::string(key) + " must be 0 or 1");
+    (key[0] == 'h' ? c->opts.hrz : key[0] == 'f' ? c->opts.fhwt : c->opts.diag) = (int)value;
+  } else if (std::strcmp(key, "backward") == 0) {
+    if (value < 0 || value > 2) return fail(TQS_EINVAL, "backward must be 0..2");
+    c->backward = (int)value;
+    return TQS_OK;
+  } else if (std::strcmp(key, "stored_cap") == 0) {
+    if (value < 0) return fail(TQS_EINVAL, "stored_cap must be >= 0");
+    c->stored_cap = value;
+    return TQS_OK;
   } else if (std::strcmp(key, "tile_bits") == 0) {
     if (value != 0 && (value < KMIN || value > KMAX)) return fail(TQS_EINVAL, "tile_bits must be 0 or 10..12");
-    c->tile_bits = (int)value;
+    c->opts.tile_bits = (int)value;
   } else {
     return fail(TQS_EINVAL, std::string("unknown option ") + key);
   }

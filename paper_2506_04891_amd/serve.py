@@ -80,7 +80,8 @@ class Result:
 def structure_key(layers):
     """Circuit structure without parameter values (sources and offsets kept)."""
     return tuple((ly.gate, ly.pattern, ly.source, ly.wire, ly.wire2, ly.offset,
-                  ly.fixed if ly.source == "FIXED" else 0.0) for ly in layers)
+                  ly.fixed if ly.source == "FIXED" else 0.0, getattr(ly, "fixed2", 0.0),
+                  getattr(ly, "fixed3", 0.0)) for ly in layers)
 
 
 def bucket(b):

@@ -20,11 +20,12 @@ _PKG = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_PKG, "libtqsim.so")
 
 GATES = {"RX": 0, "RY": 1, "RZ": 2, "H": 3, "X": 4, "Z": 5, "S": 6, "SX": 7, "GPI": 8, "GPI2": 9,
-         "CNOT": 10, "CZ": 11, "SWAP": 12, "ZZ": 13, "MS": 14, "ECR": 15}
+         "CNOT": 10, "CZ": 11, "SWAP": 12, "ZZ": 13, "MS": 14, "ECR": 15, "ROT": 16}
 PATTERNS = {"ALL": 0, "WIRE": 1, "RING": 2, "CHAIN": 3, "PAIRS_EVEN": 4, "PAIRS_ODD": 5}
 SOURCES = {"FIXED": 0, "WEIGHT": 1, "INPUT": 2}
 DTYPES = {"c64": 0, "c128": 1}
 MODES = {"auto": 0, "per_layer": 1, "fused": 2, "dense": 3}
+BACKWARDS = {"adjoint": 0, "stored": 1, "auto": 2}
 STATUS = {0: "TQS_OK", 1: "TQS_EINVAL", 2: "TQS_ENOMEM", 3: "TQS_EDEVICE", 4: "TQS_EUNSUPPORTED"}
 
 
@@ -37,7 +38,8 @@ class TqsError(RuntimeError):
 class tqs_layer(ctypes.Structure):
     _fields_ = [("gate", ctypes.c_int32), ("pattern", ctypes.c_int32), ("source", ctypes.c_int32),
                 ("wire", ctypes.c_int32), ("wire2", ctypes.c_int32), ("offset", ctypes.c_int32),
-                ("fixed_param", ctypes.c_double)]
+                ("fixed_param", ctypes.c_double), ("fixed_param2", ctypes.c_double),
+                ("fixed_param3", ctypes.c_double)]
 
 
 _lib = None
@@ -92,6 +94,8 @@ def to_c_layers(layers):
         arr[i].wire2 = int(ly.wire2)
         arr[i].offset = int(ly.offset)
         arr[i].fixed_param = float(ly.fixed)
+        arr[i].fixed_param2 = float(getattr(ly, "fixed2", 0.0))
+        arr[i].fixed_param3 = float(getattr(ly, "fixed3", 0.0))
     return arr
 
 
@@ -131,9 +135,19 @@ class Circuit:
 
     ``layers`` is a list of objects with fields gate, pattern, source, wire,
     wire2, offset, fixed (e.g. ``workloads.Layer``); enum fields may be names
-    or integers.  ``mode`` and ``tile_bits`` override the dispatcher."""
+    or integers.  ``mode`` and ``tile_bits`` override the dispatcher; ``hrz``
+    (H-Rz expansion of rotation layers), ``fhwt`` (Hadamard layers by the fast
+    Walsh-Hadamard transform) and ``diag`` ("tables": split eigenphase tables,
+    "einsum": one diagonal factor per gate) choose layer techniques.
+    ``backward``: "adjoint" (uncompute psi with the inverse layers; two state
+    sets of memory at any depth), "stored" (every forward pass keeps its
+    output in the workspace and the backward reads psi from there; the
+    adjoint_grad call must get the workspace of the forward call, untouched
+    in between), or "auto" (stored while the stored states fit
+    ``stored_cap`` bytes)."""
 
-    def __init__(self, n, layers, dtype="c64", mode="auto", tile_bits=0):
+    def __init__(self, n, layers, dtype="c64", mode="auto", tile_bits=0, backward="adjoint", stored_cap=None,
+                 hrz=False, fhwt=True, diag="tables"):
         L = lib()
         release_pending()
         self.n = int(n)
@@ -147,6 +161,17 @@ class Circuit:
             _check(L.tqs_set_option(h, b"mode", _enum(MODES, mode)))
         if tile_bits:
             _check(L.tqs_set_option(h, b"tile_bits", int(tile_bits)))
+        if hrz:
+            _check(L.tqs_set_option(h, b"hrz", 1))
+        if not fhwt:
+            _check(L.tqs_set_option(h, b"fhwt", 0))
+        if diag != "tables":
+            _check(L.tqs_set_option(h, b"diag", {"einsum": 1}[diag]))
+        self.backward = backward
+        if backward != "adjoint":
+            _check(L.tqs_set_option(h, b"backward", _enum(BACKWARDS, backward)))
+        if stored_cap is not None:
+            _check(L.tqs_set_option(h, b"stored_cap", int(stored_cap)))
         nw, nf, sb = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int64()
         _check(L.tqs_circuit_info(h, ctypes.byref(nw), ctypes.byref(nf), ctypes.byref(sb)))
         self.n_weights, self.n_features, self.state_bytes = nw.value, nf.value, sb.value
@@ -186,6 +211,11 @@ class Circuit:
         sz = ctypes.c_size_t()
         _check(lib().tqs_workspace_size(self._h, int(batch), int(bool(with_grad)), ctypes.byref(sz)))
         return sz.value
+
+    def new_workspace(self, batch, with_grad=True, device=None):
+        """A fresh (uncached) device workspace for ``batch`` samples."""
+        device = torch.device(device or "cuda")
+        return torch.empty(max(1, self.workspace_size(batch, with_grad)), dtype=torch.uint8, device=device)
 
     def workspace(self, batch, with_grad=True, device=None):
         """A cached device workspace (uint8 tensor) for ``batch`` samples."""
@@ -260,20 +290,28 @@ class QCircuitFn(torch.autograd.Function):
 
     @staticmethod
     def forward(ctx, circ, weights, features):
-        state = circ.forward(weights, features)
-        expz = circ.expval_z(state)
+        # a stored-state backward reads the forward's workspace: each forward
+        # keeps its own until its backward has run
+        ws = circ.new_workspace(features.shape[0], True, features.device) if circ.backward != "adjoint" else None
+        state = circ.forward(weights, features, ws=ws)
+        expz = circ.expval_z(state, ws=ws)
         ctx.circ = circ
         ctx.save_for_backward(weights, features)
         ctx.state = state
+        ctx.ws = ws
         return expz
 
     @staticmethod
     def backward(ctx, g):
         weights, features = ctx.saved_tensors
-        state = ctx.state if ctx.state is not None else ctx.circ.forward(weights, features)
+        ws = ctx.ws
+        if ctx.state is not None:
+            state = ctx.state
+        else:
+            state = ctx.circ.forward(weights, features, ws=ws)
         ctx.state = None
         want_x = ctx.needs_input_grad[2]
-        gw, gx = ctx.circ.adjoint_grad(weights, features, state, g.contiguous(), want_features=want_x)
+        gw, gx = ctx.circ.adjoint_grad(weights, features, state, g.contiguous(), ws=ws, want_features=want_x)
         gw = gw.to(weights.dtype) if ctx.needs_input_grad[1] else None
         gx = gx.to(features.dtype) if want_x else None
         return None, gw, gx

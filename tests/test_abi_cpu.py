@@ -153,3 +153,57 @@ def test_dropped_circuits_are_destroyed_at_safe_points():
     assert len(tqsim._released) == 0
     del keep
     tqsim.release_pending()
+
+
+def test_layer_technique_plans():
+    """Host-side plans of the selectable layer techniques (Sec. 2.4, Sec. 2.5):
+    the H-Rz expansion turns rotation layers into H and diagonal layers, the
+    fast Walsh-Hadamard transform takes the H gates, and the diagonal Einsum
+    replaces phase tables by per-gate diagonal factors."""
+    T = _lib()
+    n = 13
+    layers = [W.L("RY", "ALL", "INPUT"), W.L("CNOT", "RING"), W.L("RX", "ALL", "WEIGHT"),
+              W.L("ZZ", "RING", "WEIGHT", offset=n), W.L("H", "ALL"), W.L("RX", "ALL", "WEIGHT", offset=2 * n)]
+
+    def kinds(**kw):
+        p = T.Circuit(n, layers, "c64", mode="per_layer", **kw).plan()
+        fw = [q for q in p["passes"] if not q["bwd_only"]]
+        return p, {k: sum(q[k] for q in fw) for k in ("u1", "u2", "diag", "wht")}
+    p, base = kinds()
+    assert p["fhwt"] == 1 and p["hrz"] == 0 and p["diag"] == "tables"
+    assert base["wht"] == n and base["diag"] >= 1
+    _, nofh = kinds(fhwt=False)
+    assert nofh["wht"] == 0 and nofh["u1"] == base["u1"] + n
+    p, hrz = kinds(hrz=True)
+    assert p["hrz"] == 1
+    # two RX layers -> H, RZ, H each: 4 more Hadamard layers, their RZ as diagonal layers
+    assert hrz["wht"] == 5 * n and hrz["diag"] >= base["diag"] + 2
+    p, ein = kinds(diag="einsum")
+    assert p["diag"] == "einsum" and ein["diag"] == 0 and ein["u2"] >= n
+    # the phase and the Rot/MS gates are accepted; Rot reads three parameters per gate
+    c = T.Circuit(4, [W.L("ROT", "ALL", "WEIGHT"), W.L("MS", "PAIRS_EVEN", "WEIGHT", offset=12, fixed2=0.1,
+                                                          fixed3=0.2)], "c64")
+    assert (c.n_weights, c.n_features) == (14, 0)
+    assert T.lib().tqs_set_option(c.handle, b"hrz", 2) == 1
+    assert T.lib().tqs_set_option(c.handle, b"diag", 1) == 0
+
+
+def test_offset_overflow_is_rejected():
+    """offset + parameter count is checked in 64-bit arithmetic: an offset near
+    INT32_MAX cannot wrap into a small parameter count."""
+    st, msg = _create(4, [W.L("RX", "ALL", "WEIGHT", offset=2 ** 31 - 2)])
+    assert st == 1 and "INT32_MAX" in msg
+    st, msg = _create(4, [W.L("ROT", "ALL", "INPUT", offset=2 ** 31 - 12)])
+    assert st == 1 and "INT32_MAX" in msg
+
+
+def test_batch_near_int32_max_is_sized_in_64_bits():
+    """A batch near INT32_MAX with many samples per workgroup: the grid and the
+    workspace are computed in 64-bit arithmetic (no wrap to a small or negative
+    size)."""
+    T = _lib()
+    c = T.Circuit(4, W.circuit_rot_ring(4, 1), "c64")
+    sz = ctypes.c_size_t()
+    B = 2 ** 31 - 1
+    assert T.lib().tqs_workspace_size(c.handle, B, 1, ctypes.byref(sz)) == 0
+    assert sz.value >= B * 16 * 8

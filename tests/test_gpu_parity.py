@@ -347,3 +347,135 @@ def test_step_graph_replays_equal_eager(name):
     np.testing.assert_allclose(got[0].cpu().numpy()[rows], o["e"], atol=2e-5)
     gx = got[2].cpu().numpy()[rows]
     assert np.max(np.abs(gx - o["gx"])) / np.max(np.abs(o["gx"])) <= 1e-4
+
+
+# ------------------------------------------- stored-state backpropagation --
+
+@pytest.mark.parametrize("name,builder,dist", [
+    ("rot_ring_zz", lambda n: W.circuit_rot_ring(n, 3, "RX", ("RX", "RY", "RZ"), zz=True), "normal"),
+    ("ionq_qdi", lambda n: W.circuit_ionq(n, 4, "qdi"), "uniform2pi"),
+    ("ibm", lambda n: W.circuit_ibm(n, 4), "uniform2pi"),
+    ("fig6_qdi", lambda n: W.circuit_rz_ry_cnot(n, 4, "qdi"), "normal"),
+])
+@pytest.mark.parametrize("n,dtype,mode,B", [
+    (2, "c64", "auto", 5), (4, "c128", "dense", 3), (6, "c64", "per_layer", 17), (8, "c128", "fused", 2),
+    (12, "c64", "per_layer", 3), (14, "c64", "fused", 3), (16, "c128", "fused", 2), (18, "c64", "fused", 2),
+])
+def test_stored_state_backward(name, builder, dist, n, dtype, mode, B):
+    """The stored-state backward (the backpropagation of the paper's training:
+    forward pass outputs kept, psi read back instead of uncomputed) against
+    the oracle, in every dispatch mode."""
+    layers = builder(n)
+    w, x, g = _params(n, layers, B, seed=60 + n, dist=dist)
+    note(f"case stored {name} n={n} {dtype} mode={mode} B={B}")
+    c = T.Circuit(n, layers, dtype, mode=mode, backward="stored")
+    got = gpu_run(c, w, x, g)
+    ref = oracle_run(n, layers, w, x, g)
+    compare(got, ref, dtype, label=f"stored {name} n={n} {mode}")
+
+
+def test_stored_state_full_c3_rows():
+    """The 20-qubit workload (32 samples) with the stored-state backward: four
+    rows against the oracle, and the remaining rows' feature gradients zero."""
+    n, B, dt, layers, w, x = W.config("c3_20q_b32")
+    rows = [0, 31]
+    g = np.zeros((B, n))
+    g[rows] = W.upstream(len(rows), n, "normal", 8)
+    note("case stored full c3")
+    c = T.Circuit(n, layers, dt, backward="stored")
+    got = gpu_run(c, w, x, g)
+    ref = oracle_run(n, layers, w, x[rows], g[rows])
+    np.testing.assert_allclose(got["e"][rows], ref["e"], atol=2e-5)
+    e1 = np.max(np.abs(got["gw"] - ref["gw"])) / np.max(np.abs(ref["gw"]))
+    e2 = np.max(np.abs(got["gx"][rows] - ref["gx"])) / np.max(np.abs(ref["gx"]))
+    assert e1 <= 1e-4 and e2 <= 1e-4, (e1, e2)
+
+
+def test_auto_backward_follows_the_cap():
+    """backward="auto": stored states while they fit the cap (per batch size),
+    the adjoint beyond; both give the oracle's gradients."""
+    n = 12
+    layers = W.circuit_rot_ring(n, 3, "RY", ("RY", "RZ"))
+    state = (8 << n)
+    c = T.Circuit(n, layers, "c64", tile_bits=10, backward="auto", stored_cap=8 * state)
+    adj = T.Circuit(n, layers, "c64", tile_bits=10)
+    passes = len([p for p in c.plan()["passes"] if not p["bwd_only"]])
+    assert passes >= 2
+    for B in (1, 64):
+        stored = (passes - 1) * B * state <= 8 * state
+        extra = c.workspace_size(B, True) - adj.workspace_size(B, True)
+        assert (extra >= (passes - 1) * B * state) == stored, (B, extra)
+        w, x, g = _params(n, layers, B, seed=B)
+        note(f"case auto backward B={B} stored={stored}")
+        got = gpu_run(c, w, x, g)
+        compare(got, oracle_run(n, layers, w, x, g), "c64", label=f"auto B={B}")
+
+
+# --------------------------------- remaining gates and layer techniques --
+
+ROT_MS_CIRCUITS = [
+    ("rot", lambda n: [W.L("ROT", "ALL", "INPUT", offset=0), W.L("CNOT", "RING"), W.L("ROT", "ALL", "WEIGHT"),
+                       W.L("CZ", "CHAIN"), W.L("ROT", "WIRE", "WEIGHT", wire=n - 1, offset=3 * n),
+                       W.L("ROT", "ALL", "FIXED", fixed=0.4, fixed2=-1.1, fixed3=0.7), W.L("RX", "ALL", "WEIGHT",
+                                                                                   offset=3 * n + 3)], "normal"),
+    ("ms_phases", lambda n: [W.L("RY", "ALL", "INPUT"), W.L("GPI2", "ALL", "WEIGHT"),
+                             W.L("MS", "PAIRS_EVEN", "WEIGHT", offset=n, fixed2=0.13, fixed3=-0.41),
+                             W.L("GPI", "ALL", "WEIGHT", offset=n + n // 2),
+                             W.L("MS", "PAIRS_ODD", "INPUT", offset=n, fixed2=0.3, fixed3=0.05),
+                             W.L("MS", "PAIRS_EVEN", "FIXED", fixed=0.2, fixed2=-0.25, fixed3=0.6),
+                             W.L("RX", "ALL", "WEIGHT", offset=2 * n + n // 2)], "uniform2pi"),
+]
+
+
+@pytest.mark.parametrize("case", ROT_MS_CIRCUITS, ids=[c[0] for c in ROT_MS_CIRCUITS])
+@pytest.mark.parametrize("n,dtype,mode,B", [
+    (2, "c128", "auto", 3), (4, "c64", "dense", 5), (6, "c128", "per_layer", 3), (8, "c64", "fused", 17),
+    (12, "c64", "per_layer", 2), (14, "c64", "fused", 3), (14, "c128", "per_layer", 2), (16, "c64", "fused", 2),
+])
+def test_rot_and_phased_ms(case, n, dtype, mode, B):
+    """Appendix A's Rot(theta, phi, lambda) (three parameters per gate, from
+    weights, features or fixed values) and MS(phi0, phi1, theta) with phases,
+    against the oracle in every dispatch mode."""
+    name, build, dist = case
+    layers = build(n)
+    w, x, g = _params(n, layers, B, seed=70 + n, dist=dist)
+    note(f"case {name} n={n} {dtype} mode={mode} B={B}")
+    got = gpu_run(_circuit(n, layers, dtype, mode), w, x, g)
+    ref = oracle_run(n, layers, w, x, g)
+    compare(got, ref, dtype, label=f"{name} n={n} {mode}")
+
+
+TECHNIQUE_CIRCUITS = [
+    ("rx_ry_gpi2_rot", lambda n: [W.L("RY", "ALL", "INPUT"), W.L("RX", "ALL", "WEIGHT"), W.L("CNOT", "RING"),
+                                  W.L("RY", "ALL", "WEIGHT", offset=n), W.L("GPI2", "ALL", "WEIGHT", offset=2 * n),
+                                  W.L("CZ", "CHAIN"), W.L("ROT", "ALL", "WEIGHT", offset=3 * n),
+                                  W.L("H", "ALL"), W.L("ZZ", "RING", "WEIGHT", offset=6 * n),
+                                  W.L("RZ", "ALL", "INPUT", offset=n), W.L("H", "ALL"),
+                                  W.L("GPI", "ALL", "WEIGHT", offset=7 * n), W.L("RX", "ALL", "WEIGHT", offset=8 * n)],
+     "normal"),
+    ("fig6_qdi", lambda n: W.circuit_rz_ry_cnot(n, 3, "qdi"), "normal"),
+    ("rot_ring_zz", lambda n: W.circuit_rot_ring(n, 2, "RX", ("RX", "RY", "RZ"), zz=True), "normal"),
+]
+
+
+@pytest.mark.parametrize("case", TECHNIQUE_CIRCUITS, ids=[c[0] for c in TECHNIQUE_CIRCUITS])
+@pytest.mark.parametrize("hrz,fhwt,diag", [(True, True, "tables"), (False, False, "tables"),
+                                           (False, True, "einsum"), (True, True, "einsum")])
+@pytest.mark.parametrize("n,dtype,mode,B", [
+    (3, "c128", "per_layer", 3), (6, "c64", "dense", 5), (9, "c64", "per_layer", 3), (13, "c64", "per_layer", 2),
+    (13, "c64", "fused", 2), (14, "c128", "per_layer", 1),
+])
+def test_layer_techniques(case, hrz, fhwt, diag, n, dtype, mode, B):
+    """The layer techniques the dispatcher can select -- H-Rz expansion of
+    rotation layers (Sec. 2.5), Hadamard layers by the fast Walsh-Hadamard
+    transform (Sec. 2.5), diagonal layers by split eigenphase tables (Secs.
+    2.4.1-2.4.2) or gate by gate (diagonal Einsum, Sec. 2.4.3) -- all give the
+    oracle's states, readouts and gradients."""
+    name, build, dist = case
+    layers = build(n)
+    w, x, g = _params(n, layers, B, seed=80 + n, dist=dist)
+    note(f"case technique {name} hrz={hrz} fhwt={fhwt} diag={diag} n={n} {dtype} mode={mode} B={B}")
+    c = T.Circuit(n, layers, dtype, mode=mode, hrz=hrz, fhwt=fhwt, diag=diag)
+    got = gpu_run(c, w, x, g)
+    ref = oracle_run(n, layers, w, x, g)
+    compare(got, ref, dtype, label=f"technique {name} hrz={hrz} fhwt={fhwt} diag={diag} n={n} {mode}")

@@ -207,6 +207,48 @@ def test_h_rz_expansion_rx_and_readings():
         np.testing.assert_allclose(G.RZ(-t) @ G.RX(np.pi / 2) @ G.RZ(t), G.GPI2(phi), atol=1e-14)
 
 
+def _phase(a):
+    """diag(1, e^{ia}) from the library exponential."""
+    return expm(0.5j * a * (np.eye(2) - G.Z))
+
+
+@pytest.mark.parametrize("t,phi,lam", [(0.7, -1.3, 2.1), (-2.2, 0.4, -0.9), (0.0, 1.1, 0.3)])
+def test_rot_appendix_a(t, phi, lam):
+    """App. A Rot(theta, phi, lambda) is the phase-Ry-phase product built from
+    library exponentials, reduces to RY for phi = lambda = 0 and to a phase for
+    theta = 0, and is unitary."""
+    U = G.ROT(t, phi, lam)
+    np.testing.assert_allclose(U, _phase(phi) @ expm(-0.5j * t * G.Y) @ _phase(lam), atol=1e-14)
+    np.testing.assert_allclose(G.ROT(t, 0.0, 0.0), G.RY(t), atol=1e-15)
+    np.testing.assert_allclose(G.ROT(0.0, phi, lam), np.diag([1, np.exp(1j * (phi + lam))]), atol=1e-15)
+    np.testing.assert_allclose(U.conj().T @ U, np.eye(2), atol=1e-14)
+    h = 1e-6
+    for k, d in enumerate(G.dROT(t, phi, lam)):
+        a, b = [t, phi, lam], [t, phi, lam]
+        a[k] += h
+        b[k] -= h
+        np.testing.assert_allclose(d, (G.ROT(*a) - G.ROT(*b)) / (2 * h), atol=1e-8)
+
+
+@pytest.mark.parametrize("phi0,phi1,t", [(0.13, -0.41, 0.37), (0.5, 0.25, -0.8), (0.0, 0.0, 0.21)])
+def test_ms_with_phases(phi0, phi1, t):
+    """App. A MS(phi0, phi1, theta) as read: exp(-i pi theta P(phi1) (x) P(phi0))
+    with P the GPI matrix (library exponential), unitary, MS(theta) at zero
+    phases.  The printed entry (3, 0) would make the matrix non-unitary for
+    phi0 + phi1 not a multiple of 1/2."""
+    U = G.MSP(phi0, phi1, t)
+    np.testing.assert_allclose(U, expm(-1j * np.pi * t * np.kron(G.GPI(phi1), G.GPI(phi0))), atol=1e-14)
+    np.testing.assert_allclose(U.conj().T @ U, np.eye(4), atol=1e-14)
+    np.testing.assert_allclose(G.MSP(0.0, 0.0, t), G.MS(t), atol=1e-15)
+    printed = U.copy()
+    printed[3, 0] = -1j * np.exp(-2j * np.pi * (phi0 + phi1)) * np.sin(np.pi * t)
+    if abs(np.sin(2 * np.pi * (phi0 + phi1))) > 1e-3 and abs(np.sin(np.pi * t)) > 1e-3:
+        assert np.abs(printed.conj().T @ printed - np.eye(4)).max() > 1e-3
+    h = 1e-6
+    np.testing.assert_allclose(G.dMSP(phi0, phi1, t),
+                               (G.MSP(phi0, phi1, t + h) - G.MSP(phi0, phi1, t - h)) / (2 * h), atol=1e-8)
+
+
 # ------------------------------------------------------------ invariants ----
 
 ALL_LAYERS = [
@@ -218,6 +260,7 @@ ALL_LAYERS = [
     ("MS", "PAIRS_EVEN", "WEIGHT"), ("MS", "PAIRS_ODD", "WEIGHT"),
     ("ECR", "PAIRS_EVEN"), ("ECR", "PAIRS_ODD"), ("CNOT", "PAIRS_ODD"),
     ("RY", "ALL", "INPUT"), ("RZ", "ALL", "INPUT"),
+    ("ROT", "ALL", "WEIGHT"), ("ROT", "ALL", "INPUT"),
 ]
 
 
@@ -362,6 +405,13 @@ GRAD_CASES = [
     ("rot_ring_zz", lambda: (4, W.circuit_rot_ring(4, 1, "RX", ("RX", "RY", "RZ"), zz=True), "normal")),
     ("ionq", lambda: (4, W.circuit_ionq(4, 2), "uniform2pi")),
     ("ibm", lambda: (4, W.circuit_ibm(4, 2), "uniform2pi")),
+    ("rot_gate", lambda: (3, _layers(("ROT", "ALL", "WEIGHT"), ("CNOT", "RING"), ("ROT", "ALL", "INPUT"),
+                                     ("CZ", "CHAIN"), ("RX", "ALL", "WEIGHT")), "normal")),
+    ("ms_phases", lambda: (4, [W.L("RY", "ALL", "INPUT"), W.L("GPI2", "ALL", "WEIGHT", offset=0),
+                               W.L("MS", "PAIRS_EVEN", "WEIGHT", offset=4, fixed2=0.13, fixed3=-0.41),
+                               W.L("GPI", "ALL", "WEIGHT", offset=6),
+                               W.L("MS", "PAIRS_ODD", "INPUT", offset=4, fixed2=0.3, fixed3=0.05)],
+                           "uniform2pi")),
 ]
 
 

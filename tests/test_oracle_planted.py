@@ -59,8 +59,8 @@ def test_ring_without_wrap_pair_is_caught(monkeypatch):
 
 
 def test_adjoint_missing_factor_two_is_caught(monkeypatch):
-    orig = G.generator
-    monkeypatch.setattr(G, "generator", lambda gate, t: 0.5 * orig(gate, t))
+    orig = G.generators
+    monkeypatch.setattr(G, "generators", lambda gate, t, ph=(0.0, 0.0): [0.5 * x for x in orig(gate, t, ph)])
     _expect_failure(P.test_gradient_routes_agree, P.GRAD_CASES[0])
 
 

@@ -23,6 +23,11 @@ Each ``Layer`` names one gate type, a placement pattern and a parameter source:
 * ``source``   FIXED  -- every gate uses ``fixed``;
                WEIGHT -- gate k of the layer uses weights[offset + k];
                INPUT  -- gate k uses features[b, offset + k] for sample b.
+               ROT reads three parameters per gate, (theta, phi, lambda) at
+               offset + 3k .. offset + 3k + 2 (FIXED: fixed, fixed2, fixed3).
+* ``fixed2``, ``fixed3``  MS: the phases (phi0, phi1) in turns of
+               MS(phi0, phi1, theta) (Appendix A); ROT with FIXED source: phi
+               and lambda.
 
 Wire 0 is the most significant bit of the amplitude index (the bit order of the
 paper's binary counting matrix J in Sec. 2.4.1 and of its CNOT permutation
@@ -35,22 +40,24 @@ from collections import namedtuple
 
 import numpy as np
 
-GATES_1Q = ("RX", "RY", "RZ", "H", "X", "Z", "S", "SX", "GPI", "GPI2")
+GATES_1Q = ("RX", "RY", "RZ", "H", "X", "Z", "S", "SX", "GPI", "GPI2", "ROT")
 GATES_2Q = ("CNOT", "CZ", "SWAP", "ZZ", "MS", "ECR")
 GATES = GATES_1Q + GATES_2Q
-# gates that take one real parameter (Table 1, "Parametrized" column; GPI is
-# read as parametrized, as in the caption of the paper's Fig. 4)
-PARAM_GATES = ("RX", "RY", "RZ", "GPI", "GPI2", "ZZ", "MS")
+# parametrized gates (Table 1, "Parametrized" column; GPI is read as
+# parametrized, as in the caption of the paper's Fig. 4); ROT takes three
+PARAM_GATES = ("RX", "RY", "RZ", "GPI", "GPI2", "ZZ", "MS", "ROT")
+GATE_NPARAMS = {"ROT": 3}
 PATTERNS = ("ALL", "WIRE", "RING", "CHAIN", "PAIRS_EVEN", "PAIRS_ODD")
 SOURCES = ("FIXED", "WEIGHT", "INPUT")
 
-Layer = namedtuple("Layer", "gate pattern source wire wire2 offset fixed")
-Layer.__new__.__defaults__ = (0, 1, 0, 0.0)
+Layer = namedtuple("Layer", "gate pattern source wire wire2 offset fixed fixed2 fixed3")
+Layer.__new__.__defaults__ = (0, 1, 0, 0.0, 0.0, 0.0)
 
 
-def L(gate, pattern="ALL", source="FIXED", wire=0, wire2=1, offset=0, fixed=0.0):
+def L(gate, pattern="ALL", source="FIXED", wire=0, wire2=1, offset=0, fixed=0.0, fixed2=0.0, fixed3=0.0):
     """Convenience constructor with keyword defaults."""
-    return Layer(gate, pattern, source, int(wire), int(wire2), int(offset), float(fixed))
+    return Layer(gate, pattern, source, int(wire), int(wire2), int(offset), float(fixed), float(fixed2),
+                 float(fixed3))
 
 
 def gate_arity(gate: str) -> int:
@@ -86,7 +93,7 @@ def layer_wires(layer: Layer, n: int):
 def layer_nparams(layer: Layer, n: int) -> int:
     if layer.gate not in PARAM_GATES or layer.source == "FIXED":
         return 0
-    return len(layer_wires(layer, n))
+    return GATE_NPARAMS.get(layer.gate, 1) * len(layer_wires(layer, n))
 
 
 def circuit_counts(n: int, layers):
@@ -108,8 +115,8 @@ class _Builder:
     def __init__(self, n):
         self.n, self.layers, self.nw, self.nf = n, [], 0, 0
 
-    def add(self, gate, pattern="ALL", source="FIXED", fixed=0.0, wire=0, wire2=1):
-        ly = L(gate, pattern, source, wire, wire2, 0, fixed)
+    def add(self, gate, pattern="ALL", source="FIXED", fixed=0.0, wire=0, wire2=1, fixed2=0.0, fixed3=0.0):
+        ly = L(gate, pattern, source, wire, wire2, 0, fixed, fixed2, fixed3)
         k = layer_nparams(ly, self.n)
         if source == "WEIGHT":
             ly = ly._replace(offset=self.nw)
