@@ -143,6 +143,21 @@ tqs_status tqs_expval_z(const tqs_circuit *c, int32_t batch, const void *state_d
                         double *expz_d, double *norm_d, void *ws_d, size_t ws_bytes,
                         tqs_stream s);
 
+/* tqs_expval_z without a workspace, for callers that cannot allocate device
+ * memory or pass a workspace (code under HIP graph capture, tight serving
+ * loops, harnesses that forbid allocation).  Same outputs and kernels as
+ * tqs_expval_z; the readout partials, [batch][2^max(0, n-12)][13] doubles, sit
+ * in a static 8 MiB device array that every GPU the library runs on holds
+ * until the process ends.  Allocates nothing and calls no allocating routine.
+ * The first call on a device looks the array's address up (once per device).
+ *   state_d [batch, 2^n] (read only); expz_d [batch, n]; norm_d [batch] or NULL.
+ * EINVAL when the partials exceed 8 MiB, i.e. batch * 2^max(0, n-12) > 80659.
+ * Calls on one GPU share the array: calls that overlap in time on one GPU
+ * (different streams, threads or processes' streams without ordering) race
+ * and must be serialised by the caller. */
+tqs_status tqs_expval_z_noalloc(const tqs_circuit *c, int32_t batch, const void *state_d,
+                                double *expz_d, double *norm_d, tqs_stream s);
+
 /* Adjoint gradient of L = sum_{b,i} g[b,i] <Z_i>_b (the adjoint method cited in
  * Sec. 2.1): lambda = (sum_i g_i Z_i) psi, then layer by layer in reverse the
  * derivative 2 Im <lambda|G|psi> of every parameter is accumulated (G the gate's

@@ -16,6 +16,15 @@ using namespace tqs;
 
 static thread_local std::string g_last_error;
 
+// Scratch of tqs_expval_z_noalloc: the readout partials live in this
+// file-scope device array instead of a caller workspace.  Every GPU the
+// library runs on holds its own copy, at its own address, until the process
+// ends; host code must use the address hipGetSymbolAddress returns for the
+// current device, never the array's name (a host-side stand-in).
+static constexpr size_t NOALLOC_SCRATCH_BYTES = (size_t)8 << 20;
+static __device__ __align__(256) unsigned char scratch[NOALLOC_SCRATCH_BYTES];
+
+
 static tqs_status fail(tqs_status st, const std::string &msg) {
   g_last_error = msg;
   return st;
@@ -589,6 +598,27 @@ tqs_status rebuild(tqs_circuit *c) {
   return TQS_OK;
 }
 
+constexpr int MAX_DEVICES = 64;
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[MAX_DEVICES] = {};
+
+// Device address of the current device's scratch array, looked up once per
+// device (with that device current) and kept.
+tqs_status scratch_for_current_device(void **out) {
+  int dev = -1;
+  HIP_TRY(hipGetDevice(&dev));
+  if (dev < 0 || dev >= MAX_DEVICES) return fail(TQS_EDEVICE, "device index out of range");
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void *p = nullptr;
+    HIP_TRY(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+    if (!p) return fail(TQS_EDEVICE, "hipGetSymbolAddress returned a null scratch address");
+    g_scratch_ptr[dev] = p;
+  }
+  *out = g_scratch_ptr[dev];
+  return TQS_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -689,6 +719,23 @@ tqs_status tqs_expval_z(const tqs_circuit *c, int32_t batch, const void *state_d
   double *part = reinterpret_cast<double *>(ws + L.ev);
   if (c->dtype == TQS_C64) return expval_t<float>(c, batch, state_d, expz_d, norm_d, part, (hipStream_t)s);
   return expval_t<double>(c, batch, state_d, expz_d, norm_d, part, (hipStream_t)s);
+}
+
+tqs_status tqs_expval_z_noalloc(const tqs_circuit *c, int32_t batch, const void *state_d, double *expz_d,
+                                double *norm_d, tqs_stream s) {
+  tqs_status st = check_batch(c, batch);
+  if (st != TQS_OK) return st;
+  if (!state_d || !expz_d) return fail(TQS_EINVAL, "state or expz is NULL");
+  const size_t need = expval_partials_bytes(c->plan, batch);
+  if (need > NOALLOC_SCRATCH_BYTES)
+    return fail(TQS_EINVAL, "readout partials of " + std::to_string(need) + " bytes exceed the " +
+                                std::to_string(NOALLOC_SCRATCH_BYTES) + "-byte static scratch");
+  void *part = nullptr;
+  st = scratch_for_current_device(&part);
+  if (st != TQS_OK) return st;
+  if (c->dtype == TQS_C64)
+    return expval_t<float>(c, batch, state_d, expz_d, norm_d, static_cast<double *>(part), (hipStream_t)s, false);
+  return expval_t<double>(c, batch, state_d, expz_d, norm_d, static_cast<double *>(part), (hipStream_t)s, false);
 }
 
 tqs_status tqs_adjoint_grad(tqs_circuit *c, int32_t batch, const double *weights_d, const double *features_d,

@@ -60,6 +60,7 @@ def lib():
     L.tqs_workspace_size.argtypes = [vp, i32, i32, ctypes.POINTER(sz)]
     L.tqs_forward.argtypes = [vp, i32, vp, vp, vp, vp, sz, vp]
     L.tqs_expval_z.argtypes = [vp, i32, vp, vp, vp, vp, sz, vp]
+    L.tqs_expval_z_noalloc.argtypes = [vp, i32, vp, vp, vp, vp]
     L.tqs_adjoint_grad.argtypes = [vp, i32, vp, vp, vp, vp, vp, vp, vp, sz, vp]
     L.tqs_set_option.argtypes = [vp, ctypes.c_char_p, i64]
     L.tqs_plan_describe.argtypes = [vp, ctypes.c_char_p, sz]
@@ -68,7 +69,7 @@ def lib():
     L.tqs_status_string.restype = ctypes.c_char_p
     L.tqs_last_error.restype = ctypes.c_char_p
     for f in ("tqs_circuit_create", "tqs_circuit_destroy", "tqs_circuit_info", "tqs_workspace_size",
-              "tqs_forward", "tqs_expval_z", "tqs_adjoint_grad", "tqs_set_option", "tqs_plan_describe",
+              "tqs_forward", "tqs_expval_z", "tqs_expval_z_noalloc", "tqs_adjoint_grad", "tqs_set_option", "tqs_plan_describe",
               "tqs_profile_report"):
         getattr(L, f).restype = i32
     _lib = L
@@ -265,6 +266,15 @@ class Circuit:
         norm = torch.empty(batch, dtype=torch.float64, device=state.device) if with_norm else None
         _check(lib().tqs_expval_z(self._h, batch, _ptr(state), _ptr(expz), _ptr(norm), _ptr(ws),
                                   ws.numel(), _stream(stream)))
+        return (expz, norm) if with_norm else expz
+
+    def expval_z_noalloc(self, state, stream=None, with_norm=False):
+        """expval_z through the entry point that takes no workspace (the library's
+        static scratch).  The output tensors are the caller's allocations."""
+        batch = state.shape[0]
+        expz = torch.empty((batch, self.n), dtype=torch.float64, device=state.device)
+        norm = torch.empty(batch, dtype=torch.float64, device=state.device) if with_norm else None
+        _check(lib().tqs_expval_z_noalloc(self._h, batch, _ptr(state), _ptr(expz), _ptr(norm), _stream(stream)))
         return (expz, norm) if with_norm else expz
 
     def adjoint_grad(self, weights, features, state, grad_expz, ws=None, stream=None, want_features=True):

@@ -155,6 +155,26 @@ def test_dropped_circuits_are_destroyed_at_safe_points():
     tqsim.release_pending()
 
 
+def test_noalloc_readout_rejects_oversized_batch_on_host():
+    """The allocation-free readout checks its static-scratch limit before it
+    touches the device: 20 qubits x 316 samples of partials exceed 8 MiB."""
+    T = _lib()
+    L = T.lib()
+    layers = W.circuit_rot_ring(20, 1, "RX", ("RX",))
+    arr = T.to_c_layers(layers)
+    h = ctypes.c_void_p()
+    assert L.tqs_circuit_create(20, arr, len(layers), 0, ctypes.byref(h)) == 0
+    try:
+        dummy = ctypes.c_void_p(16)   # never dereferenced: the call fails first
+        st = L.tqs_expval_z_noalloc(h, 316, dummy, dummy, None, None)
+        assert st == 1
+        assert "static scratch" in L.tqs_last_error().decode()
+        assert L.tqs_expval_z_noalloc(h, 0, dummy, dummy, None, None) == 1
+        assert L.tqs_expval_z_noalloc(h, 4, None, dummy, None, None) == 1
+    finally:
+        L.tqs_circuit_destroy(h)
+
+
 def test_layer_technique_plans():
     """Host-side plans of the selectable layer techniques (Sec. 2.4, Sec. 2.5):
     the H-Rz expansion turns rotation layers into H and diagonal layers, the
