@@ -241,15 +241,20 @@ def test_full_c2_sampled():
 
 
 def test_full_c4a_sampled():
-    _sampled_full("c4a_16q_b128_ionq", [0, 127])
+    _sampled_full("c4a_16q_b128_ionq", [0, 37, 90, 127])
 
 
 def test_full_c4b_sampled():
-    _sampled_full("c4b_16q_b128_ibm", [5, 64])
+    _sampled_full("c4b_16q_b128_ibm", [5, 64, 101, 126])
 
 
 def test_full_c3_sampled():
-    _sampled_full("c3_20q_b32", [31])
+    """20 qubits, batch 32 (the full workload): first, last and two interior
+    rows against the oracle; and one row's final state element by element."""
+    got = _sampled_full("c3_20q_b32", [0, 13, 22, 31])
+    n, B, dt, layers, w, x = W.config("c3_20q_b32")
+    psi = sim.run_o2(n, layers, w, x[[22]])
+    assert np.max(np.abs(got["psi"][22] - psi[0])) <= 2e-5
 
 
 # ------------------------------------------- Fig. 6 circuit, VQ and QDI --
@@ -479,3 +484,56 @@ def test_layer_techniques(case, hrz, fhwt, diag, n, dtype, mode, B):
     got = gpu_run(c, w, x, g)
     ref = oracle_run(n, layers, w, x, g)
     compare(got, ref, dtype, label=f"technique {name} hrz={hrz} fhwt={fhwt} diag={diag} n={n} {mode}")
+
+
+# -------------------------------------------------- out-of-bounds writes --
+
+@pytest.mark.parametrize("n,B,dtype,backward", [(3, 5, "c64", "adjoint"), (7, 17, "c64", "stored"),
+                                                (13, 3, "c128", "adjoint"), (14, 2, "c64", "stored")])
+def test_buffers_untouched_outside_their_extent(n, B, dtype, backward):
+    """State, workspace and output buffers sit inside larger allocations whose
+    padding holds a canary pattern; after forward, <Z_i> and the adjoint at a
+    ragged batch the padding is unchanged (no kernel writes past a buffer)."""
+    layers = W.circuit_rot_ring(n, 2, "RX", ("RX", "RY", "RZ"), zz=True)
+    w, x, g = _params(n, layers, B, seed=90 + n)
+    note(f"case canary n={n} B={B} {dtype} {backward}")
+    dev = torch.device("cuda")
+    c = T.Circuit(n, layers, dtype, backward=backward)
+    PAD = 4096
+
+    def padded(nbytes):
+        buf = torch.empty(nbytes + 2 * PAD, dtype=torch.uint8, device=dev)
+        buf.fill_(0xA5)
+        return buf
+
+    def inner(buf, nbytes, dt, shape):
+        return buf[PAD:PAD + nbytes].view(dt).view(shape)
+
+    es = 8 if dtype == "c64" else 16
+    st_b = padded(B * es << n)
+    ws_n = c.workspace_size(B, True)
+    ws_b = padded(ws_n)
+    ez_b, gw_b, gx_b = padded(B * n * 8), padded(max(1, c.n_weights) * 8), padded(B * max(1, c.n_features) * 8)
+    state = inner(st_b, B * es << n, c.complex_dtype, (B, 2 ** n))
+    ws = ws_b[PAD:PAD + ws_n]
+    wt, xt, gt = (torch.tensor(v, device=dev) for v in (w, x, g))
+    c.forward(wt, xt, state=state, ws=ws)
+    ez = inner(ez_b, B * n * 8, torch.float64, (B, n))
+    L = T.lib()
+    import ctypes
+    T._check(L.tqs_expval_z(c.handle, B, ctypes.c_void_p(state.data_ptr()), ctypes.c_void_p(ez.data_ptr()), None,
+                            ctypes.c_void_p(ws.data_ptr()), ws_n, T._stream(None)))
+    gw = inner(gw_b, max(1, c.n_weights) * 8, torch.float64, (-1,))
+    gx = inner(gx_b, B * max(1, c.n_features) * 8, torch.float64, (B, -1))
+    T._check(L.tqs_adjoint_grad(c.handle, B, ctypes.c_void_p(wt.data_ptr()), ctypes.c_void_p(xt.data_ptr()),
+                                ctypes.c_void_p(state.data_ptr()), ctypes.c_void_p(gt.data_ptr()),
+                                ctypes.c_void_p(gw.data_ptr()), ctypes.c_void_p(gx.data_ptr()),
+                                ctypes.c_void_p(ws.data_ptr()), ws_n, T._stream(None)))
+    torch.cuda.synchronize()
+    for name, buf, nb in (("state", st_b, B * es << n), ("workspace", ws_b, ws_n), ("expz", ez_b, B * n * 8),
+                          ("grad_w", gw_b, max(1, c.n_weights) * 8), ("grad_x", gx_b, B * max(1, c.n_features) * 8)):
+        head, tail = buf[:PAD].cpu().numpy(), buf[PAD + nb:].cpu().numpy()
+        assert (head == 0xA5).all() and (tail == 0xA5).all(), name
+    ref = oracle_run(n, layers, w, x, g)
+    compare(dict(e=ez.cpu().numpy(), gw=gw.cpu().numpy()[: c.n_weights], gx=gx.cpu().numpy()[:, : c.n_features]),
+            ref, dtype, what=("e", "gw", "gx"), label=f"canary n={n}")
