@@ -63,6 +63,8 @@ def parse():
                    help="device memory of one forward + adjoint call vs qubits (QDI circuit)")
     p.add_argument("--technique-sweep", action="store_true",
                    help="forward time of one layer of each kind under each layer technique, n = 4..20")
+    p.add_argument("--tile-sweep", action="store_true",
+                   help="forward + adjoint at batch 1-16, n = 14..20, for tile sizes 10..12")
     p.add_argument("--backward-sweep", action="store_true",
                    help="adjoint vs stored-state backward on the benchmark workloads")
     p.add_argument("--vq-qdi-sweep", action="store_true",
@@ -533,6 +535,43 @@ def technique_sweep(iters=20):
                 print(json.dumps(row), flush=True)
 
 
+def tile_sweep(iters=10):
+    """Forward + <Z_i> + adjoint of the QDI Fig. 6 circuit at small batch for
+    tile sizes K = 10, 11, 12 (more workgroups per pass against more passes)."""
+    import torch
+    import workloads as W
+    from paper_2506_04891_amd import tqsim as T
+    dev = torch.device("cuda")
+    for B in (1, 4, 16):
+        for n in (14, 16, 18, 20):
+            row = {"n": n, "B": B}
+            for K in (10, 11, 12):
+                layers = W.circuit_rz_ry_cnot(n, 8, "qdi")
+                c = T.Circuit(n, layers, "c64", tile_bits=K)
+                w, x = W.draw_params(n, layers, B, "normal", 0)
+                wt, xt = torch.tensor(w, device=dev), torch.tensor(x, device=dev)
+                g = torch.ones((B, n), dtype=torch.float64, device=dev)
+                st = torch.empty((B, 2 ** n), dtype=c.complex_dtype, device=dev)
+                ws = c.workspace(B, True, dev)
+
+                def step():
+                    c.forward(wt, xt, state=st, ws=ws)
+                    c.expval_z(st, ws=ws)
+                    c.adjoint_grad(wt, xt, st, g, ws=ws)
+                for _ in range(3):
+                    step()
+                torch.cuda.synchronize()
+                e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                e0.record()
+                for _ in range(iters):
+                    step()
+                e1.record()
+                torch.cuda.synchronize()
+                row[f"K{K}_us"] = round(e0.elapsed_time(e1) / iters * 1e3, 1)
+                row[f"K{K}_passes"] = len(c.plan()["passes"])
+            print(json.dumps(row), flush=True)
+
+
 def backward_sweep(iters=10):
     """Adjoint (uncompute) against stored-state backward on the benchmark
     workloads: ms per forward + <Z_i> + backward step, and workspace bytes."""
@@ -720,7 +759,7 @@ def main():
     # the CPU baselines run first: the pooled one forks, which must happen
     # before anything initialises the GPU in this process
     sweep = (a.dense_sweep or a.dispatch_sweep or a.vq_qdi_sweep or a.memory_sweep or a.serve_only
-             or a.backward_sweep or a.technique_sweep)
+             or a.backward_sweep or a.technique_sweep or a.tile_sweep)
     cpu = None if (a.no_cpu_baseline or sweep) else cpu_baseline()
     ref, cpu_pool = ({}, None) if (a.no_cpu_baseline or sweep) else oracle_pool()
     import torch
@@ -746,6 +785,9 @@ def main():
         return
     if a.technique_sweep:
         technique_sweep()
+        return
+    if a.tile_sweep:
+        tile_sweep()
         return
     if a.serve_only:
         print(json.dumps(serving_bench(a.serve_requests, a.serve_max_qubits,

@@ -174,6 +174,19 @@ tqs_status tqs_adjoint_grad(tqs_circuit *c, int32_t batch, const double *weights
                             double *grad_weights_d, double *grad_features_d, void *ws_d,
                             size_t ws_bytes, tqs_stream s);
 
+/* Per-segment column sums, FP64, rows in order (deterministic):
+ *   out[s][c] = sum_{r = seg[s]}^{seg[s+1]-1} x[r][col_begin + c],
+ * for s < n_seg and c < n_cols.  x_d [rows, ld] row-major device doubles;
+ * seg_d device int32 [n_seg + 1], non-decreasing in [0, rows] (bounds are
+ * clamped to that range); out_d device [n_seg, n_cols].  The batch reduction
+ * of gradients when the rows of one launch belong to several requests (each
+ * request's weight gradient is the sum over its samples, Sec. 3 training);
+ * the serving loop uses it.  EINVAL for negative sizes or
+ * col_begin + n_cols > ld. */
+tqs_status tqs_segment_sum_rows(const double *x_d, int32_t rows, int32_t ld, int32_t col_begin,
+                                int32_t n_cols, const int32_t *seg_d, int32_t n_seg, double *out_d,
+                                tqs_stream s);
+
 /* Dispatcher override, before the first forward call.  Keys:
  *   "mode"       0 = auto, 1 = per-layer passes (one technique per layer),
  *                2 = fused passes, 3 = dense: every layer without per-sample

@@ -129,6 +129,7 @@ __device__ __forceinline__ UOp load_op(kptr<DevOp> p) {
 }
 struct UStage {
   int rbits[RB];
+  int rsorted[RB];
   int op_begin, op_end;
 };
 __device__ __forceinline__ UStage load_stage(kptr<DevStage> p) {
@@ -137,6 +138,8 @@ __device__ __forceinline__ UStage load_stage(kptr<DevStage> p) {
   s.rbits[1] = uni(p->rbits[1]);
   s.rbits[2] = uni(p->rbits[2]);
   s.rbits[3] = uni(p->rbits[3]);
+#pragma unroll
+  for (int k = 0; k < RB; ++k) s.rsorted[k] = uni(p->rsorted[k]);
   s.op_begin = uni(p->op_begin);
   s.op_end = uni(p->op_end);
   return s;
@@ -790,6 +793,28 @@ __device__ __forceinline__ T wave_sum3_transposed(T x, T y, T z, int lane) {
   v = xor16_add(v);
   v = xor32_add(v);
   return v;
+}
+
+// Eight sums reduced over the 64 lanes as one transposed tree: three butterfly
+// steps over lane bits 0-2 halve the values per lane (a lane keeps the values
+// its lane bits select; the bit-2 step pairs lane l with (l + 4) mod 16, which
+// always holds the other half of the same values), then rotations and the
+// CDNA4 row swaps reduce the one value left.  Afterwards lane l holds the total
+// of value l & 7.
+__device__ __forceinline__ double wave_sum8_transposed(const double (&v)[8], int lane) {
+  const bool b0 = lane & 1, b1 = lane & 2, b2 = lane & 4;
+  double h[4], q[2];
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+    h[i] = (b0 ? v[2 * i + 1] : v[2 * i]) + dpp_mov<0xB1>(b0 ? v[2 * i] : v[2 * i + 1]);   // lane ^ 1
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+    q[i] = (b1 ? h[2 * i + 1] : h[2 * i]) + dpp_mov<0x4E>(b1 ? h[2 * i] : h[2 * i + 1]);   // lane ^ 2
+  double x = (b2 ? q[1] : q[0]) + dpp_mov<0x124>(b2 ? q[0] : q[1]);                      // row_ror:4
+  x += dpp_mov<0x128>(x);                                                                 // row_ror:8
+  x = xor16_add(x);
+  x = xor32_add(x);
+  return x;
 }
 
 // Sum over aligned segments of 2^seg_log lanes; valid in the last lane of each segment.
@@ -1506,17 +1531,14 @@ __device__ __forceinline__ void run_stage(const Ctx<T, K> &c, const PassArgs<T> 
     __syncthreads();
     return;
   }
-  // thread tile base: the non-register tile bits, in increasing order, from tid
-  int tt = 0;
-  {
-    int cbit = 0;
-    for (int b = 0; b < K; ++b) {
-      const bool isreg = (b == S.rbits[0]) | (b == S.rbits[1]) | (b == S.rbits[2]) | (b == S.rbits[3]);
-      if (!isreg) {
-        tt |= ((c.tid >> cbit) & 1) << b;
-        ++cbit;
-      }
-    }
+  // thread tile base: the thread index spread over the non-register tile bits
+  // in increasing order -- tid with a zero inserted at each register bit's
+  // position, lowest first (each insertion sees the final positions below it)
+  int tt = c.tid;
+#pragma unroll
+  for (int k = 0; k < RB; ++k) {
+    const int p = S.rsorted[k];
+    tt = ((tt >> p) << (p + 1)) | (tt & ((1 << p) - 1));
   }
   int toff[NREG], aoff[NREG];
   {
@@ -1617,14 +1639,39 @@ __device__ __forceinline__ void run_stage(const Ctx<T, K> &c, const PassArgs<T> 
         wht16(w);
         // one entry per term with a parameter, laid out by the planner for this
         // stage: the parity-sum index m and the sign masks
-        for (int k = 0; k < op.r1; ++k) {
-          kptr<DevTermGrad> tg = a.tgrads + op.mat + k;
-          const int tacc = uni(tg->acc), m = uni(tg->m);
-          const uint32_t tmask = uniu(tg->tmask), gmask = uniu(tg->gmask);
-          const int neg = (__builtin_popcount(c.base & gmask) + __builtin_popcount((uint32_t)tt & tmask)) & 1;
-          T val = wht_pick(w, m);
-          if (neg) val = -val;
-          write_acc(c, a, val, tacc);
+        if (__builtin_amdgcn_readfirstlane(c.seg_log) == 6) {
+          // whole-wave segments: the terms' sums reduced eight at a time as one
+          // transposed tree; lane k of the wave writes term k of the chunk
+          for (int k0 = 0; k0 < op.r1; k0 += 8) {
+            double v8[8];
+            int myacc = -1;
+#pragma unroll
+            for (int q = 0; q < 8; ++q) {
+              v8[q] = 0.0;
+              if (k0 + q < op.r1) {
+                kptr<DevTermGrad> tg = a.tgrads + op.mat + k0 + q;
+                const int tacc = uni(tg->acc), m = uni(tg->m);
+                const uint32_t tmask = uniu(tg->tmask), gmask = uniu(tg->gmask);
+                const int neg =
+                    (__builtin_popcount(c.base & gmask) + __builtin_popcount((uint32_t)tt & tmask)) & 1;
+                const double val = (double)wht_pick(w, m);
+                v8[q] = neg ? -val : val;
+                if ((c.lane & 7) == q) myacc = tacc;
+              }
+            }
+            const double tot = wave_sum8_transposed(v8, c.lane);
+            if (c.lane < 8 && myacc >= 0) c.pslot[(long long)myacc * c.pstride] = tot;
+          }
+        } else {
+          for (int k = 0; k < op.r1; ++k) {
+            kptr<DevTermGrad> tg = a.tgrads + op.mat + k;
+            const int tacc = uni(tg->acc), m = uni(tg->m);
+            const uint32_t tmask = uniu(tg->tmask), gmask = uniu(tg->gmask);
+            const int neg = (__builtin_popcount(c.base & gmask) + __builtin_popcount((uint32_t)tt & tmask)) & 1;
+            T val = wht_pick(w, m);
+            if (neg) val = -val;
+            write_acc(c, a, val, tacc);
+          }
         }
       }
 #pragma unroll
@@ -2306,6 +2353,23 @@ __global__ void __launch_bounds__(NTR) k_grad_weights(const int *cptr, const Con
   }
   s = seg_sum_dpp(s, gl);
   if (valid && g == (1 << gl) - 1) gw[o] = s;
+}
+#endif
+
+// Sums of column blocks over row segments (FP64, rows in order): out[s][c] =
+// sum over rows r in [seg[s], seg[s+1]) of x[r][c0 + c].  The serving loop's
+// per-request weight gradients: the rows of one launch are the samples of
+// several requests.  Segment bounds are clamped to [0, rows].
+#ifndef TQS_PASS_TU   // defined once, in the translation unit of the host API
+__global__ void __launch_bounds__(NTR) k_segment_sum(const double *x, int rows, int ld, int c0, int nc,
+                                                     const int *seg, int n_seg, double *out) {
+  const long long t = (long long)blockIdx.x * NTR + threadIdx.x;
+  if (t >= (long long)n_seg * nc) return;
+  const int sg = (int)(t / nc), cc = (int)(t % nc);
+  const int r0 = min(max(seg[sg], 0), rows), r1 = min(max(seg[sg + 1], r0), rows);
+  double acc = 0.0;
+  for (int r = r0; r < r1; ++r) acc += x[(long long)r * ld + c0 + cc];
+  out[t] = acc;
 }
 #endif
 

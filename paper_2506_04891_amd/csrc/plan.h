@@ -78,6 +78,8 @@ struct DevOp {
 struct DevStage {
   int32_t rbits[RB];   // tile-bit index held by each register bit
   int32_t op_begin, op_end;
+  int32_t rsorted[RB]; // the same tile bits in increasing order
+  int32_t pad[2];
 };
 
 // One diagonal op's tables: TL indexed by (tile bits 0..h-1, extra bits),

@@ -1584,6 +1584,10 @@ static std::string emit(Plan &P) {
     P.dpass.push_back(d);
   }
   P.units_total = E.acc_prefix;
+  for (DevStage &st : P.dstage) {
+    for (int k = 0; k < RB; ++k) st.rsorted[k] = st.rbits[k];
+    std::sort(st.rsorted, st.rsorted + RB);
+  }
 
   // backward of the first forward pass need not store unless gradient-only passes follow
   {

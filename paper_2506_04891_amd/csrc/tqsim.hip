@@ -759,6 +759,20 @@ tqs_status tqs_adjoint_grad(tqs_circuit *c, int32_t batch, const double *weights
                            grad_features_d, ws, L, (hipStream_t)s);
 }
 
+tqs_status tqs_segment_sum_rows(const double *x_d, int32_t rows, int32_t ld, int32_t col_begin, int32_t n_cols,
+                                const int32_t *seg_d, int32_t n_seg, double *out_d, tqs_stream s) {
+  if (rows < 0 || n_cols < 0 || n_seg < 0 || col_begin < 0 || (long long)col_begin + n_cols > ld)
+    return fail(TQS_EINVAL, "bad segment-sum sizes");
+  if ((long long)n_seg * n_cols == 0) return TQS_OK;
+  if (!seg_d || !out_d || (rows > 0 && !x_d)) return fail(TQS_EINVAL, "segment-sum pointer is NULL");
+  const long long tot = (long long)n_seg * n_cols;
+  if ((tot + NTR - 1) / NTR > INT32_MAX) return fail(TQS_EINVAL, "segment-sum too large");
+  hipLaunchKernelGGL(k_segment_sum, dim3((unsigned)((tot + NTR - 1) / NTR)), dim3(NTR), 0, (hipStream_t)s, x_d, rows,
+                     ld, col_begin, n_cols, (const int *)seg_d, n_seg, out_d);
+  HIP_TRY(hipGetLastError());
+  return TQS_OK;
+}
+
 tqs_status tqs_set_option(tqs_circuit *c, const char *key, int64_t value) {
   if (!c || !key) return fail(TQS_EINVAL, "circuit or key is NULL");
   std::lock_guard<std::mutex> lk(c->mu);

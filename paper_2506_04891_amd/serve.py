@@ -464,6 +464,19 @@ class GpuExecutor:
                 gx_h = torch.empty(gx.shape, dtype=gx.dtype, pin_memory=True)
                 gx_h.copy_(gx, non_blocking=True)
                 h["gx"] = gx_h
+                nw = c.n_features - c._serve_nx
+                if nw > 0:
+                    # each request's weight gradient: the sum over its own rows,
+                    # reduced on the device in FP64
+                    from .tqsim import segment_sum_rows
+                    seg = np.zeros(len(g.reqs) + 1, dtype=np.int32)
+                    seg[1:] = np.cumsum([r.batch for r in g.reqs])
+                    seg_d = torch.from_numpy(seg).pin_memory().to(self.device, non_blocking=True)
+                    gw = segment_sum_rows(gx, c._serve_nx, nw, seg_d, stream=stream)
+                    gw_h = torch.empty(gw.shape, dtype=gw.dtype, pin_memory=True)
+                    gw_h.copy_(gw, non_blocking=True)
+                    h["gw"] = gw_h
+                    h["keep_gw"] = (seg_d, gw)
             h["event"].record(stream)
         return h
 
@@ -531,14 +544,15 @@ class GpuExecutor:
                 h["entry"]["busy"] = False
         e = h["e"].numpy()
         gx = h["gx"].numpy() if "gx" in h else None
+        gw = h["gw"].numpy() if "gw" in h else None
         nx = c._serve_nx
         out, row = [], 0
-        for r in g.reqs:
+        for i, r in enumerate(g.reqs):
             b = r.batch
             res = Result(e[row:row + b].copy())
             if gx is not None:
                 res.grad_features = gx[row:row + b, :nx].copy()
-                res.grad_weights = gx[row:row + b, nx:c.n_features].sum(axis=0)
+                res.grad_weights = gw[i].copy() if gw is not None else np.zeros(0)
             out.append(res)
             row += b
         return out

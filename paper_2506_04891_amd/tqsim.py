@@ -63,13 +63,14 @@ def lib():
     L.tqs_expval_z_noalloc.argtypes = [vp, i32, vp, vp, vp, vp]
     L.tqs_adjoint_grad.argtypes = [vp, i32, vp, vp, vp, vp, vp, vp, vp, sz, vp]
     L.tqs_set_option.argtypes = [vp, ctypes.c_char_p, i64]
+    L.tqs_segment_sum_rows.argtypes = [vp, i32, i32, i32, i32, vp, i32, vp, vp]
     L.tqs_plan_describe.argtypes = [vp, ctypes.c_char_p, sz]
     L.tqs_profile_report.argtypes = [vp, i32, ctypes.c_char_p, sz]
     L.tqs_status_string.argtypes = [i32]
     L.tqs_status_string.restype = ctypes.c_char_p
     L.tqs_last_error.restype = ctypes.c_char_p
     for f in ("tqs_circuit_create", "tqs_circuit_destroy", "tqs_circuit_info", "tqs_workspace_size",
-              "tqs_forward", "tqs_expval_z", "tqs_expval_z_noalloc", "tqs_adjoint_grad", "tqs_set_option", "tqs_plan_describe",
+              "tqs_forward", "tqs_expval_z", "tqs_expval_z_noalloc", "tqs_adjoint_grad", "tqs_set_option", "tqs_plan_describe", "tqs_segment_sum_rows",
               "tqs_profile_report"):
         getattr(L, f).restype = i32
     _lib = L
@@ -325,6 +326,21 @@ class QCircuitFn(torch.autograd.Function):
         gw = gw.to(weights.dtype) if ctx.needs_input_grad[1] else None
         gx = gx.to(features.dtype) if want_x else None
         return None, gw, gx
+
+
+def segment_sum_rows(x, col_begin, n_cols, seg, out=None, stream=None):
+    """out[s] = x[seg[s]:seg[s+1], col_begin:col_begin+n_cols].sum(0) on the device
+    (FP64, rows in order).  x: [rows, ld] float64; seg: int32 [n_seg + 1]."""
+    if x.dtype != torch.float64 or x.dim() != 2 or not x.is_contiguous():
+        raise ValueError("x must be a contiguous [rows, ld] float64 tensor")
+    if seg.dtype != torch.int32 or seg.dim() != 1 or not seg.is_contiguous():
+        raise ValueError("seg must be a contiguous int32 vector")
+    n_seg = seg.numel() - 1
+    if out is None:
+        out = torch.empty((max(0, n_seg), n_cols), dtype=torch.float64, device=x.device)
+    _check(lib().tqs_segment_sum_rows(_ptr(x), x.shape[0], x.shape[1], int(col_begin), int(n_cols), _ptr(seg),
+                                      n_seg, _ptr(out), _stream(stream)))
+    return out
 
 
 def expval(circ, weights, features):

@@ -126,3 +126,21 @@ def test_shared_parameter_shift_is_not_reported():
     sw, sx = sim.grad_param_shift(n, layers, w, x, W.upstream(2, n, "normal", 1))
     assert np.all(np.isnan(sx))
     assert not np.any(np.isnan(sw))
+
+
+def test_ms_entry_as_printed_is_caught(monkeypatch):
+    """MS(phi0, phi1, theta) with entry (3, 0) exactly as printed (App. A)."""
+    orig = G.MSP
+
+    def printed(phi0, phi1, t):
+        U = orig(phi0, phi1, t).copy()
+        U[3, 0] = -1j * np.exp(-2j * np.pi * (phi0 + phi1)) * np.sin(np.pi * t)
+        return U
+    monkeypatch.setattr(G, "MSP", printed)
+    _expect_failure(P.test_ms_with_phases, 0.13, -0.41, 0.37)
+
+
+def test_rot_with_swapped_phases_is_caught(monkeypatch):
+    orig = G.ROT
+    monkeypatch.setattr(G, "ROT", lambda t, phi, lam: orig(t, lam, phi))
+    _expect_failure(P.test_rot_appendix_a, 0.7, -1.3, 2.1)
