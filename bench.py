@@ -117,7 +117,9 @@ class Job:
             w, x = W.draw_params(n, layers, B, cfg["wdist"], cfg["seed"])
         self.name, self.n, self.B, self.grad = name, n, B, grad
         self.layers, self.w_host, self.x_host = layers, w, x
-        self.circ = T.Circuit(n, layers, dtype or dt, mode=mode)
+        # the dispatcher's backward: stored states while they fit its memory
+        # cap (8 GiB), the adjoint uncompute otherwise
+        self.circ = T.Circuit(n, layers, dtype or dt, mode=mode, backward="auto")
         dev = torch.device("cuda")
         self.w = torch.tensor(w, device=dev)
         self.x = torch.tensor(x, device=dev)
@@ -196,6 +198,7 @@ def serving_bench(n_req, n_max, fracs, seed=0, streams=4, budget=160 << 30, heav
         return reqs
 
     def run(reqs, plain, ex):
+        print(f"serving: {len(reqs)} requests, {'plain' if plain else 'continuous'}", file=sys.stderr, flush=True)
         srv = Server(ex, budget_bytes=budget, streams=streams, plain=plain, heavy_bytes=heavy)
         t0 = time.perf_counter()
         futs = []

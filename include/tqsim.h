@@ -216,11 +216,16 @@ tqs_status tqs_segment_sum_rows(const double *x_d, int32_t rows, int32_t ld, int
  *                tqs_adjoint_grad reads psi from there and writes back only
  *                lambda -- it must get the workspace of the forward call, not
  *                modified in between (tqs_expval_z may run in between);
- *                2 = stored states when they fit "stored_cap" bytes for the
- *                call's batch, adjoint otherwise (decided per batch size, the
- *                same way by every call)
+ *                2 = stored states when the adjoint's four state buffers
+ *                exceed "stored_min" bytes (they stream from HBM instead of
+ *                staying in the last-level cache: there the stored form is
+ *                faster, measured) and the stored states fit "stored_cap"
+ *                bytes; adjoint otherwise (decided per batch size, the same
+ *                way by every call)
  *   "stored_cap" bytes the stored states may take under backward = 2
  *                (default 8 GiB)
+ *   "stored_min" the adjoint state-set size above which backward = 2 stores
+ *                (default 256 MiB, the MI355X last-level cache)
  * EINVAL for an unknown key or value, or for any key but "profile" after the
  * plan has been uploaded. */
 tqs_status tqs_set_option(tqs_circuit *c, const char *key, int64_t value);

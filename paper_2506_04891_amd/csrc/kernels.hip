@@ -986,7 +986,8 @@ __device__ __forceinline__ void u1g_apply(cplx<T> (&v)[NREG], const cplx<T> (&m)
 // (fewer merge points in the op loop, so fewer register copies).
 template <typename T, int K, bool BWD, int MASK>
 __device__ __forceinline__ void u1g_step(const Ctx<T, K> &c, const PassArgs<T> &a, cplx<T> (&vp)[NREG],
-                                         cplx<T> (&vl)[NREG], const cplx<T> (&m)[RB][4], const int (&ga)[RB]) {
+                                         cplx<T> (&vl)[NREG], const cplx<T> (&m)[RB][4], const int (&ga)[RB],
+                                         bool psi) {
   if (BWD) {
 #pragma unroll
     for (int r = 0; r < RB; ++r) {
@@ -999,17 +1000,17 @@ __device__ __forceinline__ void u1g_step(const Ctx<T, K> &c, const PassArgs<T> &
       write_acc3(c, a, sx, sy, sz, ga[r]);
     }
   }
-  u1g_apply<T, MASK, BWD>(vp, m);
+  if (!BWD || psi) u1g_apply<T, MASK, BWD>(vp, m);
   if (BWD) u1g_apply<T, MASK, true>(vl, m);
 }
 
 template <typename T, int K, bool BWD>
 __device__ __forceinline__ void u1g_run(const Ctx<T, K> &c, const PassArgs<T> &a, cplx<T> (&vp)[NREG],
                                         cplx<T> (&vl)[NREG], const cplx<T> (&m)[RB][4], const int (&ga)[RB],
-                                        int mask) {
+                                        int mask, bool psi) {
   switch (mask) {
 #define X(k) \
-  case k: { TQS_CASE_MARK(G##k); u1g_step<T, K, BWD, k>(c, a, vp, vl, m, ga); TQS_CASE_MARK(eG##k); break; }
+  case k: { TQS_CASE_MARK(G##k); u1g_step<T, K, BWD, k>(c, a, vp, vl, m, ga, psi); TQS_CASE_MARK(eG##k); break; }
     X(3) X(5) X(6) X(7) X(9) X(10) X(11) X(12) X(13) X(14) X(15)
 #undef X
     default: break;
@@ -1019,13 +1020,15 @@ __device__ __forceinline__ void u1g_run(const Ctx<T, K> &c, const PassArgs<T> &a
 template <typename T, int K, bool BWD, int KIND, int A, int B, int C, int D>
 __device__ __forceinline__ void u2g_step(const Ctx<T, K> &c, const PassArgs<T> &a, cplx<T> (&vp)[NREG],
                                          cplx<T> (&vl)[NREG], kptr<cplx<T>> m0, kptr<cplx<T>> m1, int a0,
-                                         int a1) {
+                                         int a1, bool psi) {
   if (BWD && KIND == U2_MS) {
     if (a0 >= 0) write_acc(c, a, u2s_grad<T, A, B, true>(vp, vl), a0);
     if (a1 >= 0) write_acc(c, a, u2s_grad<T, C, D, true>(vp, vl), a1);
   }
-  u2s_apply<T, A, B, BWD, KIND>(vp, m0);
-  u2s_apply<T, C, D, BWD, KIND>(vp, m1);
+  if (!BWD || psi) {
+    u2s_apply<T, A, B, BWD, KIND>(vp, m0);
+    u2s_apply<T, C, D, BWD, KIND>(vp, m1);
+  }
   if (BWD) {
     u2s_apply<T, A, B, true, KIND>(vl, m0);
     u2s_apply<T, C, D, true, KIND>(vl, m1);
@@ -1035,12 +1038,12 @@ __device__ __forceinline__ void u2g_step(const Ctx<T, K> &c, const PassArgs<T> &
 template <typename T, int K, bool BWD, int KIND>
 __device__ __forceinline__ void u2g_run_k(const Ctx<T, K> &c, const PassArgs<T> &a, cplx<T> (&vp)[NREG],
                                           cplx<T> (&vl)[NREG], kptr<cplx<T>> m0, kptr<cplx<T>> m1, int a0,
-                                          int a1, int key) {
+                                          int a1, int key, bool psi) {
   switch (key) {
 #define X(p, q, r, t)                                                                          \
   case (p << 6 | q << 4 | r << 2 | t): {                                                      \
     TQS_CASE_MARK(H##p##q##r##t##_##KIND);                                                    \
-    u2g_step<T, K, BWD, KIND, p, q, r, t>(c, a, vp, vl, m0, m1, a0, a1);                       \
+    u2g_step<T, K, BWD, KIND, p, q, r, t>(c, a, vp, vl, m0, m1, a0, a1, psi);                  \
     TQS_CASE_MARK(eH##p##q##r##t##_##KIND);                                                   \
     break;                                                                                    \
   }
@@ -1480,8 +1483,11 @@ __device__ __forceinline__ void wht_dispatch(cplx<T> (&v)[NREG], int mask) {
 }
 
 template <typename T, int K, bool BWD, bool DENSE, bool DIAG>
+// psi_upto (backward): ops at processing position >= psi_upto skip the psi
+// uncompute -- the pass's last stage when psi is neither stored nor needed
+// afterwards (no later op of the stage takes a gradient from it).
 __device__ __forceinline__ void run_stage(const Ctx<T, K> &c, const PassArgs<T> &a, const UStage &S, cplx<T> *Lp,
-                          cplx<T> *Ll, const cplx<T> *tab, bool grad_only) {
+                          cplx<T> *Ll, const cplx<T> *tab, bool grad_only, int psi_upto = 1 << 30) {
   constexpr int NT = Ctx<T, K>::NT;
   const int op0_kind = uni(a.ops[S.op_begin].kind);
   if (DENSE && op0_kind == OP_DENSE) {
@@ -1560,6 +1566,7 @@ __device__ __forceinline__ void run_stage(const Ctx<T, K> &c, const PassArgs<T> 
   const int nops = S.op_end - S.op_begin;
   for (int oi = 0; oi < nops; ++oi) {
     const UOp op = load_op(a.ops + (BWD ? (S.op_end - 1 - oi) : (S.op_begin + oi)));
+    const bool upd_psi = oi < psi_upto;
     if (op.kind == OP_U1 || op.kind == OP_GRAD1) {
       kptr<cplx<T>> mg = op_mat(a, op, s_thr);
       if (BWD && (op.flags & F_GRAD)) {
@@ -1576,7 +1583,7 @@ __device__ __forceinline__ void run_stage(const Ctx<T, K> &c, const PassArgs<T> 
           kptr<cplx<T>> ms = a.mats + op.mat;
           m[0] = kld(ms, 0); m[1] = kld(ms, 1); m[2] = kld(ms, 2); m[3] = kld(ms, 3);
         }
-        u1_dispatch<T, BWD>(vp, m, op.r0, op.flags);
+        if (!BWD || upd_psi) u1_dispatch<T, BWD>(vp, m, op.r0, op.flags);
         if (BWD) u1_dispatch<T, true>(vl, m, op.r0, op.flags);
       }
     } else if (op.kind == OP_U1G) {
@@ -1593,10 +1600,10 @@ __device__ __forceinline__ void run_stage(const Ctx<T, K> &c, const PassArgs<T> 
 #pragma unroll
         for (int q = 0; q < 4; ++q) m[r][q] = kld(ms, q);
       }
-      u1g_run<T, K, BWD>(c, a, vp, vl, m, ga, op.r0);
+      u1g_run<T, K, BWD>(c, a, vp, vl, m, ga, op.r0, upd_psi);
     } else if (op.kind == OP_WHT) {
       // H is its own inverse and has no parameter
-      wht_dispatch<T>(vp, op.r0);
+      if (!BWD || upd_psi) wht_dispatch<T>(vp, op.r0);
       if (BWD) wht_dispatch<T>(vl, op.r0);
     } else if (op.kind == OP_SEQ) {
       seq_run<T, K, BWD>(c, a, vp, vl, a.seqs + op.aux, op.r0, op.sub);
@@ -1605,9 +1612,9 @@ __device__ __forceinline__ void run_stage(const Ctx<T, K> &c, const PassArgs<T> 
       kptr<cplx<T>> m0 = a.mats + uni(gp->mat[0]), m1 = a.mats + uni(gp->mat[1]);
       const int a0 = (op.flags & F_GRAD) ? uni(gp->acc[0]) : -1, a1 = (op.flags & F_GRAD) ? uni(gp->acc[1]) : -1;
       if (op.sub == U2_MS)
-        u2g_run_k<T, K, BWD, U2_MS>(c, a, vp, vl, m0, m1, a0, a1, op.r0);
+        u2g_run_k<T, K, BWD, U2_MS>(c, a, vp, vl, m0, m1, a0, a1, op.r0, upd_psi);
       else
-        u2g_run_k<T, K, BWD, U2_ECR>(c, a, vp, vl, m0, m1, a0, a1, op.r0);
+        u2g_run_k<T, K, BWD, U2_ECR>(c, a, vp, vl, m0, m1, a0, a1, op.r0, upd_psi);
     } else if (op.kind == OP_U2) {
       kptr<cplx<T>> mg = op_mat(a, op, s_thr);
       if (BWD && (op.flags & F_GRAD)) {
@@ -1620,7 +1627,7 @@ __device__ __forceinline__ void run_stage(const Ctx<T, K> &c, const PassArgs<T> 
           g = u2_grad_dispatch(vp, vl, op.r0, op.r1, op.aux);
         write_acc(c, a, g, op.acc);
       }
-      u2_apply_any<T, BWD>(vp, mg, op.r0, op.r1, op.sub);
+      if (!BWD || upd_psi) u2_apply_any<T, BWD>(vp, mg, op.r0, op.r1, op.sub);
       if (BWD) u2_apply_any<T, true>(vl, mg, op.r0, op.r1, op.sub);
     } else if (DENSE && op.kind == OP_GRAD2) {
       if (BWD && (op.flags & F_GRAD)) {
@@ -1678,15 +1685,16 @@ __device__ __forceinline__ void run_stage(const Ctx<T, K> &c, const PassArgs<T> 
       for (int j = 0; j < NREG; ++j) {
         cplx<T> d = diag_phase<T>(dv, tab, toff[j]);
         if (BWD) d = cconj(d);
-        vp[j] = cmul(vp[j], d);
+        if (!BWD || upd_psi) vp[j] = cmul(vp[j], d);
         if (BWD) vl[j] = cmul(vl[j], d);
       }
     }
   }
   if (!grad_only) {
+    const bool psi_live = !BWD || psi_upto > nops;
 #pragma unroll
     for (int j = 0; j < NREG; ++j) {
-      Lp[aoff[j]] = vp[j];
+      if (psi_live) Lp[aoff[j]] = vp[j];
       if (BWD) Ll[aoff[j]] = vl[j];
     }
   }
@@ -2023,9 +2031,29 @@ __attribute__((amdgpu_waves_per_eu(PassOcc<T, BWD, DENSE>::waves))) k_pass(PassA
 
   // ---------------- stages ----------------
   const int ns = uni(P->n_stages), sb = uni(P->stage_begin);
+  // backward: when psi is neither stored nor read after this pass (stored
+  // states, or the first pass without embedding gradients), the psi uncompute
+  // of the last stage is dead from its last gradient-taking op on
+  const bool psi_dead_end = BWD && !DENSE && (!uni(a.store_psi) || uni(P->skip_bwd_store)) &&
+                            uni(P->n_grad_stages) == 0 && uni(P->outside_mask) == 0;
   for (int si = 0; si < ns; ++si) {
     const UStage S = load_stage(a.stages + sb + (BWD ? (ns - 1 - si) : si));
-    run_stage<T, K, BWD, DENSE, DIAG>(c, a, S, Lp, Ll, tab, false);
+    int psi_upto = 1 << 30;
+    if (psi_dead_end && si == ns - 1) {
+      // processing position of the last op that takes a gradient (-1: none);
+      // brick-layer programs need psi between their inner steps
+      const int nops = S.op_end - S.op_begin;
+      int last = -1;
+      bool seq = false;
+      for (int oi = 0; oi < nops; ++oi) {
+        const int k = S.op_end - 1 - oi;
+        const int kind = uni(a.ops[k].kind), flags = uni(a.ops[k].flags);
+        if (kind == OP_SEQ || kind == OP_PERM || kind == OP_DENSE) seq = true;
+        if (flags & F_GRAD) last = oi;
+      }
+      if (!seq) psi_upto = last < 0 ? 0 : last;
+    }
+    run_stage<T, K, BWD, DENSE, DIAG>(c, a, S, Lp, Ll, tab, false, psi_upto);
   }
   if (BWD) {
     const int ng = uni(P->n_grad_stages), gsb = uni(P->grad_stage_begin);

@@ -69,10 +69,12 @@ struct tqs_circuit {
   // backward: 0 = adjoint with uncompute (psi rebuilt pass by pass with the
   // inverse layers), 1 = stored states (every forward pass keeps its output;
   // the backward reads psi from there and writes only lambda), 2 = stored when
-  // the stored states fit stored_cap bytes and the plan has at most
-  // STORED_AUTO_MAX_PASSES forward passes, adjoint otherwise
+  // the adjoint's four state buffers exceed stored_min bytes (they no longer
+  // stay in the last-level cache), the stored states fit stored_cap bytes and
+  // the plan has at most STORED_AUTO_MAX_PASSES forward passes; adjoint otherwise
   int backward = 0;
   long long stored_cap = 8ll << 30;
+  long long stored_min = 256ll << 20;
   std::mutex mu;
   bool uploaded = false;
   int device = -1;
@@ -194,8 +196,9 @@ bool use_stored(const tqs_circuit *c, int B) {
   if (c->backward != 2) return false;
   const Plan &P = c->plan;
   const int m = forward_passes(P);
-  const double bytes = (double)(m - 1) * (double)((size_t)B << P.n) * (P.dtype ? 16.0 : 8.0);
-  return m <= STORED_AUTO_MAX_PASSES && bytes <= (double)c->stored_cap;
+  const double state = (double)((size_t)B << P.n) * (P.dtype ? 16.0 : 8.0);
+  return m <= STORED_AUTO_MAX_PASSES && (double)(m - 1) * state <= (double)c->stored_cap &&
+         4.0 * state > (double)c->stored_min;
 }
 
 WsLayout layout(const Plan &P, int B, bool grad, bool stored) {
@@ -792,9 +795,9 @@ tqs_status tqs_set_option(tqs_circuit *c, const char *key, int64_t value) {
     if (value < 0 || value > 2) return fail(TQS_EINVAL, "backward must be 0..2");
     c->backward = (int)value;
     return TQS_OK;
-  } else if (std::strcmp(key, "stored_cap") == 0) {
-    if (value < 0) return fail(TQS_EINVAL, "stored_cap must be >= 0");
-    c->stored_cap = value;
+  } else if (std::strcmp(key, "stored_cap") == 0 || std::strcmp(key, "stored_min") == 0) {
+    if (value < 0) return fail(TQS_EINVAL, std::string(key) + " must be >= 0");
+    (key[7] == 'c' ? c->stored_cap : c->stored_min) = value;
     return TQS_OK;
   } else if (std::strcmp(key, "tile_bits") == 0) {
     if (value != 0 && (value < KMIN || value > KMAX)) return fail(TQS_EINVAL, "tile_bits must be 0 or 10..12");

@@ -145,11 +145,12 @@ class Circuit:
     sets of memory at any depth), "stored" (every forward pass keeps its
     output in the workspace and the backward reads psi from there; the
     adjoint_grad call must get the workspace of the forward call, untouched
-    in between), or "auto" (stored while the stored states fit
+    in between), or "auto" (stored when the adjoint's state set outgrows the
+    last-level cache, ``stored_min`` bytes, and the stored states fit
     ``stored_cap`` bytes)."""
 
     def __init__(self, n, layers, dtype="c64", mode="auto", tile_bits=0, backward="adjoint", stored_cap=None,
-                 hrz=False, fhwt=True, diag="tables"):
+                 hrz=False, fhwt=True, diag="tables", stored_min=None):
         L = lib()
         release_pending()
         self.n = int(n)
@@ -174,6 +175,8 @@ class Circuit:
             _check(L.tqs_set_option(h, b"backward", _enum(BACKWARDS, backward)))
         if stored_cap is not None:
             _check(L.tqs_set_option(h, b"stored_cap", int(stored_cap)))
+        if stored_min is not None:
+            _check(L.tqs_set_option(h, b"stored_min", int(stored_min)))
         nw, nf, sb = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int64()
         _check(L.tqs_circuit_info(h, ctypes.byref(nw), ctypes.byref(nf), ctypes.byref(sb)))
         self.n_weights, self.n_features, self.state_bytes = nw.value, nf.value, sb.value

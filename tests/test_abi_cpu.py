@@ -227,3 +227,20 @@ def test_batch_near_int32_max_is_sized_in_64_bits():
     B = 2 ** 31 - 1
     assert T.lib().tqs_workspace_size(c.handle, B, 1, ctypes.byref(sz)) == 0
     assert sz.value >= B * 16 * 8
+
+
+def test_auto_backward_by_state_set_size():
+    """backward="auto" on the benchmark shapes: the 16-qubit batch-128 state set
+    (4 x 64 MiB) stays with the adjoint; the 20-qubit batch-32 one (4 x 256
+    MiB, beyond the last-level cache) takes the stored states (more workspace)."""
+    T = _lib()
+    for name, stored in (("c4a_16q_b128_ionq", False), ("c3_20q_b32", True)):
+        n, B, dt, layers, w, x = W.config(name)
+        auto = T.Circuit(n, layers, dt, backward="auto")
+        adj = T.Circuit(n, layers, dt)
+        extra = auto.workspace_size(B, True) - adj.workspace_size(B, True)
+        assert (extra > 0) == stored, (name, extra)
+    # the options are validated
+    c = T.Circuit(4, W.circuit_rot_ring(4, 1), "c64")
+    assert T.lib().tqs_set_option(c.handle, b"stored_min", -1) == 1
+    assert T.lib().tqs_set_option(c.handle, b"backward", 3) == 1

@@ -398,11 +398,12 @@ def test_stored_state_full_c3_rows():
 
 def test_auto_backward_follows_the_cap():
     """backward="auto": stored states while they fit the cap (per batch size),
-    the adjoint beyond; both give the oracle's gradients."""
+    the adjoint beyond; both give the oracle's gradients.  (The state-set
+    threshold is set to zero here so that the cap alone decides.)"""
     n = 12
     layers = W.circuit_rot_ring(n, 3, "RY", ("RY", "RZ"))
     state = (8 << n)
-    c = T.Circuit(n, layers, "c64", tile_bits=10, backward="auto", stored_cap=8 * state)
+    c = T.Circuit(n, layers, "c64", tile_bits=10, backward="auto", stored_cap=8 * state, stored_min=0)
     adj = T.Circuit(n, layers, "c64", tile_bits=10)
     passes = len([p for p in c.plan()["passes"] if not p["bwd_only"]])
     assert passes >= 2
