@@ -103,7 +103,12 @@ typedef struct tqs_circuit tqs_circuit;
 typedef struct ihipStream_t *tqs_stream;   /* hipStream_t; NULL = default stream */
 
 /* Validate a layer list and compile its execution plan (host only; no device
- * memory is touched until the first forward call).  n_qubits in [1, 30];
+ * memory is touched until the first forward call or tqs_circuit_prepare).
+ * The layer list is the paper's circuit model: uniform layers of gates, each
+ * layer one unitary on the whole state (Sec. 1, Sec. 2.2.1); the plan picks a
+ * technique per layer from its properties -- diagonal, permutation, real,
+ * 1- or 2-qubit (Table 1, Sec. 3) -- and fuses layers into tile passes.
+ * n_qubits in [1, 30];
  * parameters of a layer must fit in the weights / features implied by the
  * largest offset + count.  *out receives a new circuit (free with
  * tqs_circuit_destroy).  EINVAL for: n out of range, an unknown gate / pattern /
@@ -111,6 +116,12 @@ typedef struct ihipStream_t *tqs_stream;   /* hipStream_t; NULL = default stream
  * wires, PAIRS patterns with odd n, negative offsets. */
 tqs_status tqs_circuit_create(int32_t n_qubits, const tqs_layer *layers, int32_t n_layers,
                               tqs_dtype dtype, tqs_circuit **out);
+
+/* Upload the circuit's plan to the current device (one allocation and a
+ * synchronous copy) if it is not there yet, so that later calls enqueue work
+ * only -- e.g. before the calls are captured into a HIP graph.  Options other
+ * than "profile" cannot change afterwards.  EDEVICE on a HIP failure. */
+tqs_status tqs_circuit_prepare(tqs_circuit *c);
 
 /* Free a circuit and its device tables.  Safe on NULL. */
 tqs_status tqs_circuit_destroy(tqs_circuit *c);
@@ -126,7 +137,11 @@ tqs_status tqs_circuit_info(const tqs_circuit *c, int32_t *n_weights, int32_t *n
 tqs_status tqs_workspace_size(const tqs_circuit *c, int32_t batch, int32_t with_grad,
                               size_t *bytes);
 
-/* Forward pass: psi_b = U_L ... U_1 |0...0> for every sample.
+/* Forward pass: psi_b = U_L ... U_1 |0...0> for every sample -- each layer's
+ * unitary applied in order to the state vector (Sec. 1, Sec. 2.2.1), the
+ * features entering the input-driven layers (angle embedding, Sec. 3).
+ * The first call on a circuit uploads its plan (one device allocation and a
+ * synchronous copy) unless tqs_circuit_prepare ran before.
  *   weights_d   device, [n_weights] double (may be NULL if n_weights == 0)
  *   features_d  device, [batch, n_features] double row-major (NULL if none)
  *   state_d     device, [batch, 2^n] complex of the circuit's dtype; written
@@ -137,7 +152,9 @@ tqs_status tqs_forward(tqs_circuit *c, int32_t batch, const double *weights_d,
                        tqs_stream s);
 
 /* Readout: expz[b, i] = <psi_b| Z_i |psi_b> (Z_i = +1 on bit value 0 of wire i),
- * accumulated in double; norm[b] = <psi_b|psi_b> when norm_d != NULL.
+ * accumulated in double; norm[b] = <psi_b|psi_b> when norm_d != NULL.  This is
+ * K_Rz^T |psi|^2 with K_Rz = 1 - 2J, J the binary counting matrix (Sec. 2.4.1);
+ * the single-qubit observables of the paper's circuits (Figs. 6 and 11).
  *   state_d [batch, 2^n] (read only); expz_d [batch, n] double; norm_d [batch]. */
 tqs_status tqs_expval_z(const tqs_circuit *c, int32_t batch, const void *state_d,
                         double *expz_d, double *norm_d, void *ws_d, size_t ws_bytes,

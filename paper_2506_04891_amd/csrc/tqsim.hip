@@ -658,6 +658,11 @@ tqs_status tqs_circuit_create(int32_t n_qubits, const tqs_layer *layers, int32_t
   return TQS_OK;
 }
 
+tqs_status tqs_circuit_prepare(tqs_circuit *c) {
+  if (!c) return fail(TQS_EINVAL, "circuit is NULL");
+  return upload(c);
+}
+
 tqs_status tqs_circuit_destroy(tqs_circuit *c) {
   if (!c) return TQS_OK;
   for (auto &r : c->pending) {

@@ -56,6 +56,7 @@ def lib():
     vp, i32, i64, sz = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_size_t
     L.tqs_circuit_create.argtypes = [i32, ctypes.POINTER(tqs_layer), i32, i32, ctypes.POINTER(vp)]
     L.tqs_circuit_destroy.argtypes = [vp]
+    L.tqs_circuit_prepare.argtypes = [vp]
     L.tqs_circuit_info.argtypes = [vp, ctypes.POINTER(i32), ctypes.POINTER(i32), ctypes.POINTER(i64)]
     L.tqs_workspace_size.argtypes = [vp, i32, i32, ctypes.POINTER(sz)]
     L.tqs_forward.argtypes = [vp, i32, vp, vp, vp, vp, sz, vp]
@@ -69,9 +70,9 @@ def lib():
     L.tqs_status_string.argtypes = [i32]
     L.tqs_status_string.restype = ctypes.c_char_p
     L.tqs_last_error.restype = ctypes.c_char_p
-    for f in ("tqs_circuit_create", "tqs_circuit_destroy", "tqs_circuit_info", "tqs_workspace_size",
-              "tqs_forward", "tqs_expval_z", "tqs_expval_z_noalloc", "tqs_adjoint_grad", "tqs_set_option", "tqs_plan_describe", "tqs_segment_sum_rows",
-              "tqs_profile_report"):
+    for f in ("tqs_circuit_create", "tqs_circuit_destroy", "tqs_circuit_prepare", "tqs_circuit_info",
+              "tqs_workspace_size", "tqs_forward", "tqs_expval_z", "tqs_expval_z_noalloc", "tqs_adjoint_grad",
+              "tqs_set_option", "tqs_plan_describe", "tqs_segment_sum_rows", "tqs_profile_report"):
         getattr(L, f).restype = i32
     _lib = L
     return L
@@ -197,6 +198,11 @@ class Circuit:
     @property
     def complex_dtype(self):
         return torch.complex64 if self.dtype == "c64" else torch.complex128
+
+    def prepare(self):
+        """Upload the plan now (before capturing calls into a HIP graph)."""
+        _check(lib().tqs_circuit_prepare(self._h))
+        return self
 
     def plan(self):
         buf = ctypes.create_string_buffer(1 << 20)

@@ -538,3 +538,33 @@ def test_buffers_untouched_outside_their_extent(n, B, dtype, backward):
     ref = oracle_run(n, layers, w, x, g)
     compare(dict(e=ez.cpu().numpy(), gw=gw.cpu().numpy()[: c.n_weights], gx=gx.cpu().numpy()[:, : c.n_features]),
             ref, dtype, what=("e", "gw", "gx"), label=f"canary n={n}")
+
+
+def test_prepared_cold_circuit_captures_into_a_graph():
+    """A circuit never run before, prepared with tqs_circuit_prepare, can have
+    its first forward / readout / adjoint calls captured into a HIP graph;
+    replays equal an eager step of an identical circuit bit for bit."""
+    n, B = 10, 6
+    layers = W.circuit_ibm(n, 3)
+    w, x, g = _params(n, layers, B, seed=5, dist="uniform2pi")
+    dev = torch.device("cuda")
+    wt, xt, gt = (torch.tensor(v, device=dev) for v in (w, x, g))
+    note("case prepared capture")
+    cold = _circuit(n, layers, "c64").prepare()
+    st = torch.empty((B, 2 ** n), dtype=cold.complex_dtype, device=dev)
+    ws = cold.workspace(B, True, dev)
+    torch.cuda.synchronize()
+    graph = torch.cuda.CUDAGraph()
+    side = torch.cuda.Stream()
+    with torch.cuda.graph(graph, stream=side):
+        cold.forward(wt, xt, state=st, ws=ws)
+        e = cold.expval_z(st, ws=ws)
+        gw, gx = cold.adjoint_grad(wt, xt, st, gt, ws=ws)
+    warm = _circuit(n, layers, "c64")
+    ref = gpu_run(warm, w, x, g)
+    for _ in range(2):
+        graph.replay()
+        torch.cuda.synchronize()
+        np.testing.assert_array_equal(e.cpu().numpy(), ref["e"])
+        np.testing.assert_array_equal(gw.cpu().numpy(), ref["gw"])
+        np.testing.assert_array_equal(gx.cpu().numpy(), ref["gx"])
