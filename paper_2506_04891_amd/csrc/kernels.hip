@@ -131,6 +131,9 @@ struct UStage {
   int rbits[RB];
   int rsorted[RB];
   int op_begin, op_end;
+  int flags;
+  int dense_next[2];
+  int fwd_next;
 };
 __device__ __forceinline__ UStage load_stage(kptr<DevStage> p) {
   UStage s;
@@ -142,6 +145,10 @@ __device__ __forceinline__ UStage load_stage(kptr<DevStage> p) {
   for (int k = 0; k < RB; ++k) s.rsorted[k] = uni(p->rsorted[k]);
   s.op_begin = uni(p->op_begin);
   s.op_end = uni(p->op_end);
+  s.flags = uni(p->flags);
+  s.dense_next[0] = uni(p->dense_next[0]);
+  s.dense_next[1] = uni(p->dense_next[1]);
+  s.fwd_next = uni(p->fwd_next);
   return s;
 }
 
@@ -845,6 +852,12 @@ template <typename T, int K>
 struct Ctx {
   static constexpr int NT = 1 << (K - RB);
   int tid, lane;
+  // passes with full-layer matrix ops: wave group `sub` of `nsub`, each running
+  // every stage on its own copy of the tile; group 0 writes the tile and the
+  // partials of the other ops, the gradient-only ops are shared out among the
+  // groups (pwriter_own / pwriter3_own: the writer flags without that rule)
+  int sub, nsub;
+  int pwriter_own, pwriter3_own;
   int n, nv;
   int multi;            // several samples per workgroup
   int sample0;          // first sample of the workgroup
@@ -1289,10 +1302,11 @@ __device__ __forceinline__ void build_diag_tables(const Ctx<T, K> &c, const Pass
     const int n_ent = (1 << (h + nx)) + (1 << (K - h));
     if (gt >= 0) {
       const cplx<T> *src = a.diag_tabs + gt + (long long)tile * n_ent;
-      for (int idx = c.tid; idx < n_ent; idx += Ctx<T, K>::NT) tab[off + idx] = src[idx];
+      for (int idx = c.tid + c.sub * Ctx<T, K>::NT; idx < n_ent; idx += Ctx<T, K>::NT * c.nsub)
+        tab[off + idx] = src[idx];
       continue;
     }
-    for (int idx = c.tid; idx < n_ent; idx += Ctx<T, K>::NT) {
+    for (int idx = c.tid + c.sub * Ctx<T, K>::NT; idx < n_ent; idx += Ctx<T, K>::NT * c.nsub) {
       const double ang = diag_entry_angle(dg, a.terms, a.dbl, a.dbl_ps, a.dbl_ps_stride, c.base, c.sample0, idx);
       double s, co;
       sincos(ang, &s, &co);
@@ -1382,72 +1396,126 @@ struct Mfma<double> {
   static __device__ __forceinline__ int row(int lane, int r) { return (lane >> 4) + 4 * r; }
 };
 
-// X <- U X (or U^dagger X) for every sample of the tile: out[j][s] =
-// sum_k U[j][k] X[k][s], X[k][s] = tile element s * 2^NV + k.  U sits in LDS
-// with row stride 2^NV + 1.  Complex products as four real MFMA products;
-// 16 x 16 output blocks spread over the waves; results go to the scratch tile
-// S, then back to X.
-template <typename T, int K, int NV, bool ADJ>
-__device__ __forceinline__ void dense_apply(const Ctx<T, K> &c, cplx<T> *X, cplx<T> *S, const cplx<T> *U) {
-  typedef typename Mfma<T>::V V;
-  constexpr int NT = Ctx<T, K>::NT;
-  constexpr int DIM = 1 << NV, LDU = DIM + 1;
-  constexpr int RBK = DIM / 16, CBK = (1 << (K - NV)) / 16;
-  const int lane = c.tid & 63, wave = c.tid >> 6;
-  for (int blk = wave; blk < RBK * CBK; blk += NT / 64) {
-    const int mb = blk % RBK, nb = blk / RBK;
-    V acc_r = {0, 0, 0, 0}, acc_i = {0, 0, 0, 0};
-    const int ar = mb * 16 + (lane & 15);
-    const int bj = nb * 16 + (lane & 15);
-#pragma unroll
-    for (int kb = 0; kb < DIM / 4; ++kb) {
-      const int kk = kb * 4 + (lane >> 4);
-      const cplx<T> u = ADJ ? cconj(U[kk * LDU + ar]) : U[ar * LDU + kk];
-      const cplx<T> x = X[swz<T>(bj * DIM + kk)];
-      acc_r = Mfma<T>::run(u.x, x.x, acc_r);
-      acc_r = Mfma<T>::run(-u.y, x.y, acc_r);
-      acc_i = Mfma<T>::run(u.x, x.y, acc_i);
-      acc_i = Mfma<T>::run(u.y, x.x, acc_i);
-    }
-#pragma unroll
-    for (int r = 0; r < 4; ++r) {
-      const int row = mb * 16 + Mfma<T>::row(lane, r);
-      S[swz<T>(bj * DIM + row)] = cmk<T>(acc_r[r], acc_i[r]);
-    }
+// Ordering between two stages.  The next reader of an element may be another
+// wave of the workgroup, so in general a workgroup barrier.  In passes with
+// full-layer matrix ops (one wave per copy of the tile, NT = 64) every stage
+// but the matrix ops touches only the wave's own copy, and a wave's LDS
+// accesses complete in order: keeping the compiler from moving LDS accesses
+// across this point suffices.
+template <int K, bool DENSE>
+__device__ __forceinline__ void stage_sync() {
+  if constexpr (DENSE && (1 << (K - RB)) == 64) {
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+  } else {
+    __syncthreads();
   }
-  __syncthreads();
-#pragma unroll
-  for (int i = 0; i < NREG; ++i) {
-    const int t = swz<T>(c.tid + i * NT);
-    X[t] = S[t];
-  }
-  __syncthreads();
 }
 
-// One dense stage: stage the layer matrix in LDS, then apply it (forward) or
-// its adjoint to psi and lambda (backward).
+// Workgroup barrier for LDS traffic alone: global loads still in flight (the
+// next matrix op's rows of U) are not waited for.
+__device__ __forceinline__ void lds_barrier() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+  __builtin_amdgcn_s_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+}
+
+// Registers carried between the full-layer matrix ops of a pass: the next op's
+// rows of U (lane layout of dense_fetch), fetched while the current op runs.
+template <typename T, bool DENSE>
+struct DenseCarry {
+  cplx<T> u[DENSE ? 16 : 1];
+};
+
+// The wave's MFMA A-operand of a 2^NV x 2^NV layer matrix: row block
+// sub % (2^NV / 16), lane l holding row (l % 16) of the block and column
+// 4 kb + l / 16 in u[kb].  Backward takes U^dagger: the same lanes read the
+// transposed entry, and the conjugate is applied when the products are summed.
 template <typename T, int K, int NV, bool BWD>
-__device__ __forceinline__ void dense_stage(const Ctx<T, K> &c, cplx<T> *Lp, cplx<T> *Ll, cplx<T> *scr,
-                                            kptr<cplx<T>> Ug) {
-  constexpr int NT = Ctx<T, K>::NT;
-  constexpr int DIM = 1 << NV, LDU = DIM + 1;
-  constexpr int PER = DIM * DIM / NT;          // elements per thread
-  constexpr int CH = PER < 8 ? PER : 8;         // loads kept in flight together
-  cplx<T> *U = scr + (1 << K);
+__device__ __forceinline__ void dense_fetch(const Ctx<T, K> &c, kptr<cplx<T>> Ug, cplx<T> (&u)[16]) {
+  constexpr int DIM = 1 << NV, KB = DIM / 4, RBK = DIM / 16;
+  const int ar = (c.sub % RBK) * 16 + (c.lane & 15);
 #pragma unroll
-  for (int i0 = 0; i0 < PER; i0 += CH) {
-    cplx<T> t[CH];
+  for (int kb = 0; kb < KB; ++kb) {
+    const int kk = kb * 4 + (c.lane >> 4);
+    u[kb] = kld(Ug, BWD ? kk * DIM + ar : ar * DIM + kk);
+  }
+  // every entry defined on every path, so that the carry stays in registers
 #pragma unroll
-    for (int q = 0; q < CH; ++q) t[q] = kld(Ug, (i0 + q) * NT + c.tid);
+  for (int kb = KB; kb < 16; ++kb) u[kb] = cmk<T>(0, 0);
+}
+
+template <typename T, int K, bool BWD>
+__device__ __forceinline__ void dense_fetch_nv(const Ctx<T, K> &c, kptr<cplx<T>> Ug, cplx<T> (&u)[16]) {
+  switch (c.nv) {
+    case 4: dense_fetch<T, K, 4, BWD>(c, Ug, u); break;
+    case 5: dense_fetch<T, K, 5, BWD>(c, Ug, u); break;
+    default: dense_fetch<T, K, 6, BWD>(c, Ug, u); break;
+  }
+}
+
+// A full-layer matrix op (the unitary operation of Sec. 2.2.1) on the matrix
+// cores: X <- U X forward, U^dagger X backward (on psi and on lambda), for every
+// sample of the tile: out[j][s] = sum_k U[j][k] X[k][s] with X[k][s] = tile
+// element s * 2^NV + k.  A pass with such ops runs DENSE_SUBS waves per tile,
+// each on its own copy of the tile (copies CS elements apart); with K = 10 the
+// product has exactly DENSE_SUBS 16 x 16 output blocks (2^NV / 16 row blocks
+// times 2^(K-NV) / 16 sample blocks), one per wave.  The wave's rows of U
+// arrive in `carry` (fetched during the previous op, or before the first);
+// the next op's rows (matrix offset `next`, -1 if none) are requested at once.
+// Four independent real MFMA chains (re*re, im*im, re*im, im*re); once every
+// wave has read its copy, each writes its block into all copies.  The reads
+// are of the wave's own copy, written last by the wave itself or before the
+// barrier that ends the previous matrix op.
+template <typename T, int K, int NV, bool BWD>
+__device__ __forceinline__ void dense_stage(const Ctx<T, K> &c, cplx<T> *Lp, cplx<T> *Ll, cplx<T> (&carry)[16],
+                                            kptr<cplx<T>> mats, int next) {
+  typedef typename Mfma<T>::V V;
+  constexpr int DIM = 1 << NV, KB = DIM / 4, RBK = DIM / 16;
+  static_assert(RBK * ((1 << (K - NV)) / 16) == DENSE_SUBS, "one 16 x 16 output block per wave");
+  constexpr int CS = (BWD ? 2 : 1) << K;
+  const int lane = c.lane;
+  const int mb = c.sub % RBK, nb = c.sub / RBK;
+  const int bj = nb * 16 + (lane & 15);
+  cplx<T> u[KB];
 #pragma unroll
-    for (int q = 0; q < CH; ++q) {
-      const int i = (i0 + q) * NT + c.tid;
-      U[(i / DIM) * LDU + (i % DIM)] = t[q];
+  for (int kb = 0; kb < KB; ++kb) u[kb] = carry[kb];
+  if (next >= 0) dense_fetch<T, K, NV, BWD>(c, mats + next, carry);
+  stage_sync<K, true>();
+  const V z = {0, 0, 0, 0};
+  V p0 = z, p1 = z, p2 = z, p3 = z, l0 = z, l1 = z, l2 = z, l3 = z;
+#pragma unroll
+  for (int kb = 0; kb < KB; ++kb) {
+    const int e = swz<T>(bj * DIM + kb * 4 + (lane >> 4));
+    const cplx<T> x = Lp[e];
+    p0 = Mfma<T>::run(u[kb].x, x.x, p0);
+    p1 = Mfma<T>::run(u[kb].y, x.y, p1);
+    p2 = Mfma<T>::run(u[kb].x, x.y, p2);
+    p3 = Mfma<T>::run(u[kb].y, x.x, p3);
+    if (BWD) {
+      const cplx<T> y = Ll[e];
+      l0 = Mfma<T>::run(u[kb].x, y.x, l0);
+      l1 = Mfma<T>::run(u[kb].y, y.y, l1);
+      l2 = Mfma<T>::run(u[kb].x, y.y, l2);
+      l3 = Mfma<T>::run(u[kb].y, y.x, l3);
     }
   }
-  __syncthreads();
-  dense_apply<T, K, NV, BWD>(c, Lp, scr, U);
-  if (BWD) dense_apply<T, K, NV, true>(c, Ll, scr, U);
+  lds_barrier();
+  cplx<T> *base = Lp - (long long)c.sub * CS;
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+    const int e = swz<T>(bj * DIM + mb * 16 + Mfma<T>::row(lane, r));
+    // backward: u holds U entries, the product is with their conjugates
+    const cplx<T> vp = BWD ? cmk<T>(p0[r] + p1[r], p2[r] - p3[r]) : cmk<T>(p0[r] - p1[r], p2[r] + p3[r]);
+#pragma unroll
+    for (int q = 0; q < DENSE_SUBS; ++q) base[q * CS + e] = vp;
+    if (BWD) {
+      const cplx<T> vl = cmk<T>(l0[r] + l1[r], l2[r] - l3[r]);
+#pragma unroll
+      for (int q = 0; q < DENSE_SUBS; ++q) base[q * CS + (1 << K) + e] = vl;
+    }
+  }
+  lds_barrier();
 }
 
 // Hadamard gates on the register bits of MASK as the fast Walsh-Hadamard
@@ -1487,20 +1555,21 @@ template <typename T, int K, bool BWD, bool DENSE, bool DIAG>
 // uncompute -- the pass's last stage when psi is neither stored nor needed
 // afterwards (no later op of the stage takes a gradient from it).
 __device__ __forceinline__ void run_stage(const Ctx<T, K> &c, const PassArgs<T> &a, const UStage &S, cplx<T> *Lp,
-                          cplx<T> *Ll, const cplx<T> *tab, bool grad_only, int psi_upto = 1 << 30) {
+                          cplx<T> *Ll, const cplx<T> *tab, DenseCarry<T, DENSE> &dc, bool grad_only,
+                          int psi_upto = 1 << 30) {
   constexpr int NT = Ctx<T, K>::NT;
-  const int op0_kind = uni(a.ops[S.op_begin].kind);
-  if (DENSE && op0_kind == OP_DENSE) {
-    kptr<cplx<T>> U = a.mats + uni(a.ops[S.op_begin].mat);
-    cplx<T> *scr = const_cast<cplx<T> *>(tab) + uni(a.pass->dense_off);
-    __syncthreads();
-    switch (c.nv) {
-      case 4: dense_stage<T, K, 4, BWD>(c, Lp, Ll, scr, U); break;
-      case 5: dense_stage<T, K, 5, BWD>(c, Lp, Ll, scr, U); break;
-      default: dense_stage<T, K, 6, BWD>(c, Lp, Ll, scr, U); break;
+  if constexpr (DENSE) {
+    if (S.flags & STAGE_DENSE) {
+      const int next = S.dense_next[BWD ? 1 : 0];
+      switch (c.nv) {
+        case 4: dense_stage<T, K, 4, BWD>(c, Lp, Ll, dc.u, a.mats, next); break;
+        case 5: dense_stage<T, K, 5, BWD>(c, Lp, Ll, dc.u, a.mats, next); break;
+        default: dense_stage<T, K, 6, BWD>(c, Lp, Ll, dc.u, a.mats, next); break;
+      }
+      return;
     }
-    return;
   }
+  const int op0_kind = uni(a.ops[S.op_begin].kind);
   if (op0_kind == OP_PERM) {
     // in-tile permutation: forward new[t] = old[src(t)], backward the inverse
     kptr<DevPerm> pm = a.perms + uni(a.ops[S.op_begin].aux);
@@ -1526,7 +1595,7 @@ __device__ __forceinline__ void run_stage(const Ctx<T, K> &c, const PassArgs<T> 
       vp[i] = Lp[swz<T>(rd)];
       if (BWD) vl[i] = Ll[swz<T>(rd)];
     }
-    __syncthreads();
+    stage_sync<K, DENSE>();
 #pragma unroll
     for (int i = 0; i < NREG; ++i) {
       const int t = c.tid + i * NT;
@@ -1534,7 +1603,7 @@ __device__ __forceinline__ void run_stage(const Ctx<T, K> &c, const PassArgs<T> 
       Lp[swz<T>(wr)] = vp[i];
       if (BWD) Ll[swz<T>(wr)] = vl[i];
     }
-    __syncthreads();
+    stage_sync<K, DENSE>();
     return;
   }
   // thread tile base: the thread index spread over the non-register tile bits
@@ -1556,6 +1625,12 @@ __device__ __forceinline__ void run_stage(const Ctx<T, K> &c, const PassArgs<T> 
       aoff[j] = st ^ ((j & 1) ? s0 : 0) ^ ((j & 2) ? s1 : 0) ^ ((j & 4) ? s2 : 0) ^ ((j & 8) ? s3 : 0);
     }
   }
+  const int nops = S.op_end - S.op_begin;
+  // gradient-only stage of a full-layer matrix pass: the wave group's own op,
+  // requested before the tile is read
+  const bool gonly = DENSE && (S.flags & STAGE_GRAD_ONLY);
+  UOp own;
+  if (gonly && c.sub < nops) own = load_op(a.ops + (BWD ? (S.op_end - 1 - c.sub) : (S.op_begin + c.sub)));
   cplx<T> vp[NREG], vl[NREG];
 #pragma unroll
   for (int j = 0; j < NREG; ++j) {
@@ -1563,16 +1638,30 @@ __device__ __forceinline__ void run_stage(const Ctx<T, K> &c, const PassArgs<T> 
     if (BWD) vl[j] = Ll[aoff[j]];
   }
   const int s_thr = thread_sample(c, a.batch);
-  const int nops = S.op_end - S.op_begin;
   for (int oi = 0; oi < nops; ++oi) {
-    const UOp op = load_op(a.ops + (BWD ? (S.op_end - 1 - oi) : (S.op_begin + oi)));
+    // gradient-only stages of full-layer matrix passes: the wave group takes
+    // its own ops alone (see the ownership rule below)
+    if (gonly && oi % c.nsub != c.sub) continue;
+    const UOp op = (gonly && oi == c.sub) ? own : load_op(a.ops + (BWD ? (S.op_end - 1 - oi) : (S.op_begin + oi)));
     const bool upd_psi = oi < psi_upto;
     if (op.kind == OP_U1 || op.kind == OP_GRAD1) {
       kptr<cplx<T>> mg = op_mat(a, op, s_thr);
       if (BWD && (op.flags & F_GRAD)) {
-        T sx = 0, sy = 0, sz = 0;
-        u1_grad_dispatch(vp, vl, op.r0, sx, sy, sz);
-        write_acc3(c, a, sx, sy, sz, op.acc);
+        if (DENSE && op.kind == OP_GRAD1) {
+          // a gradient-only op: taken by one wave group, in turn
+          if (oi % c.nsub == c.sub) {
+            Ctx<T, K> co = c;
+            co.pwriter = c.pwriter_own;
+            co.pwriter3 = c.pwriter3_own;
+            T sx = 0, sy = 0, sz = 0;
+            u1_grad_dispatch(vp, vl, op.r0, sx, sy, sz);
+            write_acc3(co, a, sx, sy, sz, op.acc);
+          }
+        } else {
+          T sx = 0, sy = 0, sz = 0;
+          u1_grad_dispatch(vp, vl, op.r0, sx, sy, sz);
+          write_acc3(c, a, sx, sy, sz, op.acc);
+        }
       }
       if (op.kind == OP_U1) {
         cplx<T> m[4];
@@ -1630,10 +1719,12 @@ __device__ __forceinline__ void run_stage(const Ctx<T, K> &c, const PassArgs<T> 
       if (!BWD || upd_psi) u2_apply_any<T, BWD>(vp, mg, op.r0, op.r1, op.sub);
       if (BWD) u2_apply_any<T, true>(vl, mg, op.r0, op.r1, op.sub);
     } else if (DENSE && op.kind == OP_GRAD2) {
-      if (BWD && (op.flags & F_GRAD)) {
+      if (BWD && (op.flags & F_GRAD) && oi % c.nsub == c.sub) {
+        Ctx<T, K> co = c;
+        co.pwriter = c.pwriter_own;
         const T g = (op.aux == (1 | (1 << 2))) ? u2s_grad_dispatch<T, true>(vp, vl, op.r0, op.r1)
                                                 : u2s_grad_dispatch<T, false>(vp, vl, op.r0, op.r1);
-        write_acc(c, a, g, op.acc);
+        write_acc(co, a, g, op.acc);
       }
     } else if (DIAG && op.kind == OP_DIAG) {
       kptr<DevDiag> dg = a.diags + uni(a.pass->diag_begin) + op.aux;
@@ -1667,7 +1758,7 @@ __device__ __forceinline__ void run_stage(const Ctx<T, K> &c, const PassArgs<T> 
               }
             }
             const double tot = wave_sum8_transposed(v8, c.lane);
-            if (c.lane < 8 && myacc >= 0) c.pslot[(long long)myacc * c.pstride] = tot;
+            if (c.sub == 0 && c.lane < 8 && myacc >= 0) c.pslot[(long long)myacc * c.pstride] = tot;
           }
         } else {
           for (int k = 0; k < op.r1; ++k) {
@@ -1698,7 +1789,7 @@ __device__ __forceinline__ void run_stage(const Ctx<T, K> &c, const PassArgs<T> 
       if (BWD) Ll[aoff[j]] = vl[j];
     }
   }
-  __syncthreads();
+  stage_sync<K, DENSE>();
 }
 
 // Embedding gradients of wires outside the embedding pass's tile, at the end of
@@ -1790,19 +1881,24 @@ struct PassOcc {
 // DIAG = false: the variant for passes without diagonal layers (no phase
 // tables, no diagonal op code).
 template <typename T, int K, bool BWD, bool DENSE, bool DIAG>
-__global__ void __launch_bounds__(1 << (K - RB))
+__global__ void __launch_bounds__((1 << (K - RB)) * (DENSE ? DENSE_SUBS : 1))
 __attribute__((amdgpu_waves_per_eu(PassOcc<T, BWD, DENSE>::waves))) k_pass(PassArgs<T> a) {
   constexpr int NT = 1 << (K - RB);
   constexpr int NE = 1 << K;
+  constexpr int NSUB = DENSE ? DENSE_SUBS : 1;
   extern __shared__ __align__(16) unsigned char smem[];
-  cplx<T> *Lp = reinterpret_cast<cplx<T> *>(smem);
+  Ctx<T, K> c;
+  c.tid = NSUB > 1 ? (int)(threadIdx.x & (NT - 1)) : (int)threadIdx.x;
+  c.lane = threadIdx.x & 63;
+  c.sub = NSUB > 1 ? (int)(threadIdx.x >> (K - RB)) : 0;
+  c.nsub = NSUB;
+  // the wave group's copy of the tile: psi, then lambda (backward); the tables
+  // after the last copy
+  cplx<T> *Lp = reinterpret_cast<cplx<T> *>(smem) + (long long)c.sub * (BWD ? 2 : 1) * NE;
   cplx<T> *Ll = Lp + NE;
-  cplx<T> *tab = Lp + (BWD ? 2 : 1) * NE;
+  cplx<T> *tab = reinterpret_cast<cplx<T> *>(smem) + NSUB * (BWD ? 2 : 1) * NE;
   kptr<DevPass> P = a.pass;
 
-  Ctx<T, K> c;
-  c.tid = threadIdx.x;
-  c.lane = threadIdx.x & 63;
   c.n = uni(P->n);
   c.nv = uni(P->nv);
   c.multi = c.nv < K;
@@ -1827,7 +1923,12 @@ __attribute__((amdgpu_waves_per_eu(PassOcc<T, BWD, DENSE>::waves))) k_pass(PassA
   c.pslot = nullptr;
   c.pstride = 0;
   c.pwriter = 0;
+  c.pslot3 = nullptr;
+  c.pwriter3 = 0;
   if (BWD) set_partial_slot(c, a.partials, a.acc_region, a.batch, a.units);
+  c.pwriter_own = c.pwriter;
+  c.pwriter3_own = c.pwriter3;
+  if (c.sub != 0) c.pwriter = c.pwriter3 = 0;
 
   if (DIAG && uni(P->n_diag) > 0)
     build_diag_tables<T, K>(c, a, tab, c.multi ? 0 : (int)((uint32_t)wg & ((1u << (c.nv - K)) - 1u)));
@@ -2031,15 +2132,35 @@ __attribute__((amdgpu_waves_per_eu(PassOcc<T, BWD, DENSE>::waves))) k_pass(PassA
 
   // ---------------- stages ----------------
   const int ns = uni(P->n_stages), sb = uni(P->stage_begin);
+  DenseCarry<T, DENSE> dc;
+  if constexpr (DENSE) {
+    const int m0 = uni(P->dense_first_mat[BWD ? 1 : 0]);
+    if (m0 >= 0) dense_fetch_nv<T, K, BWD>(c, a.mats + m0, dc.u);
+  }
   // backward: when psi is neither stored nor read after this pass (stored
   // states, or the first pass without embedding gradients), the psi uncompute
   // of the last stage is dead from its last gradient-taking op on
   const bool psi_dead_end = BWD && !DENSE && (!uni(a.store_psi) || uni(P->skip_bwd_store)) &&
                             uni(P->n_grad_stages) == 0 && uni(P->outside_mask) == 0;
-  for (int si = 0; si < ns; ++si) {
-    const UStage S = load_stage(a.stages + sb + (BWD ? (ns - 1 - si) : si));
+  // full-layer matrix passes (one wave per SIMD) request the next stage's
+  // descriptor while the current stage runs, and forward step over the
+  // gradient-only stages
+  UStage Snext;
+  if (DENSE && ns > 0) Snext = load_stage(a.stages + sb + (BWD ? ns - 1 : 0));
+  for (int si = 0; si < ns;) {
+    UStage S;
+    int step = 1;
+    if constexpr (DENSE) {
+      S = Snext;
+      step = BWD ? 1 : S.fwd_next;
+      if (si + step < ns) Snext = load_stage(a.stages + sb + (BWD ? (ns - 1 - si - step) : (si + step)));
+    } else {
+      S = load_stage(a.stages + sb + (BWD ? (ns - 1 - si) : si));
+    }
+    const int scur = si;
+    si += step;
     int psi_upto = 1 << 30;
-    if (psi_dead_end && si == ns - 1) {
+    if (psi_dead_end && scur == ns - 1) {
       // processing position of the last op that takes a gradient (-1: none);
       // brick-layer programs need psi between their inner steps
       const int nops = S.op_end - S.op_begin;
@@ -2053,13 +2174,20 @@ __attribute__((amdgpu_waves_per_eu(PassOcc<T, BWD, DENSE>::waves))) k_pass(PassA
       }
       if (!seq) psi_upto = last < 0 ? 0 : last;
     }
-    run_stage<T, K, BWD, DENSE, DIAG>(c, a, S, Lp, Ll, tab, false, psi_upto);
+    // stages of gradient sums alone (full-layer matrix passes): nothing to do
+    // forward, nothing to write back
+    if (DENSE && (S.flags & STAGE_GRAD_ONLY)) {
+      if (!BWD) continue;
+      run_stage<T, K, BWD, DENSE, DIAG>(c, a, S, Lp, Ll, tab, dc, true);
+      continue;
+    }
+    run_stage<T, K, BWD, DENSE, DIAG>(c, a, S, Lp, Ll, tab, dc, false, psi_upto);
   }
   if (BWD) {
     const int ng = uni(P->n_grad_stages), gsb = uni(P->grad_stage_begin);
     for (int si = 0; si < ng; ++si) {
       const UStage S = load_stage(a.stages + gsb + si);
-      run_stage<T, K, BWD, DENSE, DIAG>(c, a, S, Lp, Ll, tab, true);
+      run_stage<T, K, BWD, DENSE, DIAG>(c, a, S, Lp, Ll, tab, dc, true);
     }
     const uint32_t omask = uniu(P->outside_mask);
     if (omask && !c.multi) outside_embed_grads(c, a, P, Ll, omask);
@@ -2067,6 +2195,7 @@ __attribute__((amdgpu_waves_per_eu(PassOcc<T, BWD, DENSE>::waves))) k_pass(PassA
   }
 
   // ---------------- store ----------------
+  if (NSUB > 1 && c.sub != 0) return;   // every copy holds the same tile
   // an opaque copy of the thread's index bits: otherwise the compiler keeps the
   // load phase's element indices alive through every stage to reuse them here
   uint32_t ptid_s = ptid;
@@ -2372,12 +2501,39 @@ __global__ void __launch_bounds__(NTR) k_grad_weights(const int *cptr, const Con
   double s = 0.0;
   if (valid) {
     const int p = (int)o;
-    for (int b = g; b < batch; b += (1 << gl))
-      for (int ci = cptr[p]; ci < cptr[p + 1]; ++ci) {
-        const Contrib cb = contribs[ci];
-        const double *co = cb.coef_ps ? dbl_ps + (size_t)b * dbl_ps_stride + cb.coef : dbl + cb.coef;
-        for (int k = 0; k < cb.n; ++k) s += co[k] * A[(long long)(cb.acc + k) * batch + b];
+    const int G = 1 << gl;
+    // contributions outermost: the loads of the batch loops below do not wait
+    // on one another, so four of them are kept in flight per lane
+    for (int ci = cptr[p]; ci < cptr[p + 1]; ++ci) {
+      const Contrib cb = contribs[ci];
+      for (int k = 0; k < cb.n; ++k) {
+        const double *Ak = A + (long long)(cb.acc + k) * batch;
+        double t0 = 0.0, t1 = 0.0, t2 = 0.0, t3 = 0.0;
+        if (cb.coef_ps) {
+          const double *co = dbl_ps + cb.coef + k;
+          int b = g;
+          for (; b + 3 * G < batch; b += 4 * G) {
+            t0 += co[(size_t)b * dbl_ps_stride] * Ak[b];
+            t1 += co[(size_t)(b + G) * dbl_ps_stride] * Ak[b + G];
+            t2 += co[(size_t)(b + 2 * G) * dbl_ps_stride] * Ak[b + 2 * G];
+            t3 += co[(size_t)(b + 3 * G) * dbl_ps_stride] * Ak[b + 3 * G];
+          }
+          for (; b < batch; b += G) t0 += co[(size_t)b * dbl_ps_stride] * Ak[b];
+          s += (t0 + t1) + (t2 + t3);
+        } else {
+          // a shared coefficient: the batch sum first
+          int b = g;
+          for (; b + 3 * G < batch; b += 4 * G) {
+            t0 += Ak[b];
+            t1 += Ak[b + G];
+            t2 += Ak[b + 2 * G];
+            t3 += Ak[b + 3 * G];
+          }
+          for (; b < batch; b += G) t0 += Ak[b];
+          s += dbl[cb.coef + k] * ((t0 + t1) + (t2 + t3));
+        }
       }
+    }
   }
   s = seg_sum_dpp(s, gl);
   if (valid && g == (1 << gl) - 1) gw[o] = s;

@@ -20,11 +20,15 @@ constexpr int RB = 4;                 // register bits per stage
 constexpr int NREG = 1 << RB;         // amplitudes per thread per stage
 constexpr int KMIN = 10;              // smallest tile (64 threads)
 constexpr int KMAX = 12;              // largest tile (256 threads)
+constexpr int DENSE_SUBS = 4;         // waves per tile (each with a copy of the tile) in passes with full-layer matrix ops
 constexpr int NQMAX = 30;             // largest qubit count
 constexpr int MAX_STAGES = 48;        // per pass
 constexpr int MAX_OPS = 512;          // per pass
 constexpr int MAX_DIAG_EXTRA = 3;     // extra index bits of a split diagonal table
 constexpr int MAX_DIAG_OPS = 4;       // diagonal ops with tables per pass
+
+constexpr int32_t STAGE_GRAD_ONLY = 1;
+constexpr int32_t STAGE_DENSE = 2;
 
 enum OpKind : int32_t {
   OP_U1 = 1,     // 2x2 on register bit r0
@@ -79,7 +83,9 @@ struct DevStage {
   int32_t rbits[RB];   // tile-bit index held by each register bit
   int32_t op_begin, op_end;
   int32_t rsorted[RB]; // the same tile bits in increasing order
-  int32_t pad[2];
+  int32_t flags;       // STAGE_GRAD_ONLY: every op only takes gradient sums; STAGE_DENSE: a full-layer matrix op
+  int32_t dense_next[2];   // STAGE_DENSE: matrix of the pass's next such op forward [0] / backward [1], -1 if none
+  int32_t fwd_next;        // stages to the next one the forward runs (gradient-only stages skipped)
 };
 
 // One diagonal op's tables: TL indexed by (tile bits 0..h-1, extra bits),
@@ -177,8 +183,9 @@ struct DevPass {
   int32_t acc_region;        // offset of this pass's partials (doubles)
   int32_t grad_stage_begin, n_grad_stages;   // backward-only tail stages (embed gradients)
   int32_t skip_bwd_store;    // backward of the first pass need not store
-  int32_t diag_lds;          // complex elements of diag tables (and dense scratch) in LDS
-  int32_t dense_off;         // LDS offset (elements, after the tiles) of the dense-op scratch, -1 if none
+  int32_t diag_lds;          // complex elements of diag tables in LDS
+  int32_t has_dense;         // 1 if the pass holds full-layer matrix ops (K = 10, DENSE_SUBS waves per tile)
+  int32_t dense_first_mat[2];   // matrix of the first full-layer op forward [0] and backward [1], -1 if none
   // embedding pass, backward: state bits outside the tile whose embed gradients are
   // taken from the product-state environment (X, Y, Z sums per bit, ascending),
   // starting at accumulator outside_acc

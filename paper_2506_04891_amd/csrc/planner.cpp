@@ -1223,7 +1223,7 @@ static std::string emit(Plan &P) {
       d.store_c = pp.store_map.c;
     }
     d.load_mode = pp.load_mode;
-    d.dense_off = -1;
+    d.has_dense = 0;
     d.embed_mat = embed_mat;
     d.embed_per_sample = P.embed_per_sample;
     d.diag_begin = (int)P.ddiag.size();
@@ -1410,11 +1410,7 @@ static std::string emit(Plan &P) {
       } else if (op.kind == IR_DENSE) {
         o.kind = OP_DENSE;
         o.mat = op_mat[oi_ir];
-        if (d.dense_off < 0) {
-          // scratch tile, then the layer matrix staged with a padded row stride
-          d.dense_off = d.diag_lds;
-          d.diag_lds += (1 << K) + (1 << P.nv) * ((1 << P.nv) + 1);
-        }
+        d.has_dense = 1;
       } else if (op.kind == IR_GRAD1) {
         o.kind = OP_GRAD1;
         o.r0 = ridx(tix.at(op.bits[0]));
@@ -1587,6 +1583,39 @@ static std::string emit(Plan &P) {
   for (DevStage &st : P.dstage) {
     for (int k = 0; k < RB; ++k) st.rsorted[k] = st.rbits[k];
     std::sort(st.rsorted, st.rsorted + RB);
+    bool grad_only = st.op_end > st.op_begin;
+    for (int o = st.op_begin; o < st.op_end; ++o)
+      grad_only = grad_only && (P.dop[o].kind == OP_GRAD1 || P.dop[o].kind == OP_GRAD2);
+    st.flags = grad_only ? STAGE_GRAD_ONLY : 0;
+  }
+  // forward: distance to the next stage that changes the state
+  for (const DevPass &d : P.dpass)
+    for (int si = d.stage_begin; si < d.stage_begin + d.n_stages; ++si) {
+      int k = si + 1;
+      while (k < d.stage_begin + d.n_stages && (P.dstage[k].flags & STAGE_GRAD_ONLY)) ++k;
+      P.dstage[si].fwd_next = k - si;
+    }
+  // full-layer matrix ops name the matrix of the pass's next one in either
+  // direction, so that a pass fetches it while the current one runs
+  for (DevPass &d : P.dpass) {
+    d.dense_first_mat[0] = d.dense_first_mat[1] = -1;
+    std::vector<int> dops;
+    for (int si = d.stage_begin; si < d.stage_begin + d.n_stages; ++si)
+      for (int o = P.dstage[si].op_begin; o < P.dstage[si].op_end; ++o)
+        if (P.dop[o].kind == OP_DENSE) dops.push_back(o);
+    for (size_t k = 0; k < dops.size(); ++k) {
+      DevStage *st = nullptr;
+      for (int si = d.stage_begin; si < d.stage_begin + d.n_stages; ++si)
+        if (P.dstage[si].op_begin == dops[k]) st = &P.dstage[si];
+      if (!st) return "internal: a full-layer matrix op must open its stage";
+      st->flags |= STAGE_DENSE;
+      st->dense_next[0] = k + 1 < dops.size() ? P.dop[dops[k + 1]].mat : -1;
+      st->dense_next[1] = k > 0 ? P.dop[dops[k - 1]].mat : -1;
+    }
+    if (!dops.empty()) {
+      d.dense_first_mat[0] = P.dop[dops.front()].mat;
+      d.dense_first_mat[1] = P.dop[dops.back()].mat;
+    }
   }
 
   // backward of the first forward pass need not store unless gradient-only passes follow

@@ -332,7 +332,11 @@ tqs_status launch_pass(tqs_circuit *c, int pi, int B, const cplx<T> *src0, cplx<
   if (grid_ll > INT32_MAX) return fail(TQS_EINVAL, "batch too large: pass grid exceeds 2^31 - 1 workgroups");
   const int grid = (int)grid_ll;
   const size_t es = sizeof(cplx<T>);
-  const size_t lds = ((size_t)(BWD ? 2 : 1) * ((size_t)1 << d.K) + (size_t)d.diag_lds) * es;
+  // one copy of the tile (psi, and lambda backward) per wave group: DENSE_SUBS
+  // copies in passes with full-layer matrix ops
+  const size_t copies = d.has_dense ? DENSE_SUBS : 1;
+  const size_t lds = (copies * (BWD ? 2 : 1) * ((size_t)1 << d.K) + (size_t)d.diag_lds) * es;
+  if (lds > 160 * 1024) return fail(TQS_EUNSUPPORTED, "pass needs more than 160 KiB of LDS");
   double bytes = 0, flops = 0;
   if (c->profile) {
     const double amps = (double)B * (double)(1ll << P.n);
@@ -349,8 +353,8 @@ tqs_status launch_pass(tqs_circuit *c, int pi, int B, const cplx<T> *src0, cplx<
                          (sizeof(T) == 8 ? "_c128" : "_c64"), bytes, flops);
   // passes holding full-layer matrix ops use their own instantiation, so that
   // the matrix-core code does not raise the register use of the others
-  if (!PassLaunch<T, BWD>::run(a, d.K, d.dense_off >= 0, d.n_diag > 0, grid, lds, s))
-    return fail(TQS_EUNSUPPORTED, d.dense_off >= 0 ? "dense layers need a 10-bit tile" : "tile size not built");
+  if (!PassLaunch<T, BWD>::run(a, d.K, d.has_dense != 0, d.n_diag > 0, grid, lds, s))
+    return fail(TQS_EUNSUPPORTED, d.has_dense ? "dense layers need a 10-bit tile" : "tile size not built");
   ps.end();
   HIP_TRY(hipGetLastError());
   return TQS_OK;
