@@ -126,6 +126,24 @@ def test_dense_circuits(name, n, builder, dist, B):
     compare(got, ref, "c64", label=f"dense {name} n={n} B={B}")
 
 
+@pytest.mark.parametrize("dt", ["c64", "c128"])
+@pytest.mark.parametrize("n", [4, 5, 6])
+def test_dense_multi_tile(n, dt):
+    """Dense mode over many sample tiles with a ragged last one (129 samples:
+    16, 32 or 64 per tile), in both precisions: every wave's output block, the
+    layer rows fetched one op ahead, and the gradient-only stages shared out
+    among the waves, against the oracle on every row."""
+    layers = W.circuit_rot_ring(n, 3, "RY", ("RY", "RZ"))
+    B = 129
+    w, x, g = _params(n, layers, B, seed=400 + n, dist="normal")
+    note(f"case dense multi-tile n={n} B={B} {dt}")
+    c = _circuit(n, layers, dt, "dense")
+    assert c.plan()["mode"] == "dense"
+    got = gpu_run(c, w, x, g)
+    ref = oracle_run(n, layers, w, x, g)
+    compare(got, ref, dt, label=f"dense multi-tile n={n} {dt}")
+
+
 def test_config1_dense_exact():
     n, B, dt, layers, w, x = W.config("c1_4q_b16")
     g = W.upstream(B, n, "normal", 1)
