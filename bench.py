@@ -385,7 +385,7 @@ def vq_qdi_sweep(iters=20):
     Figs. 12-13's on the IonQ and IBM native-gate circuits of App. B (8
     blocks): forward (+ <Z_i>), backward (adjoint) and total time per call
     against the number of qubits, at batch 1 and 64, for VQ and QDI encodings
-    (c64)."""
+    (c64); eager calls, and the same calls replayed as HIP graphs."""
     import torch
     import workloads as W
     from paper_2506_04891_amd import tqsim as T
@@ -427,6 +427,21 @@ def vq_qdi_sweep(iters=20):
                     torch.cuda.synchronize()
                     row[name + "_us"] = round(e0.elapsed_time(e1) / iters * 1e3, 1)
                 row["bwd_us"] = round(row["total_us"] - row["fwd_us"], 1)
+                # the same calls replayed as HIP graphs (tqsim.StepGraph): no
+                # per-launch host cost
+                for name, gr in (("fwd", None), ("total", g)):
+                    sg = T.StepGraph(c, wt, xt, gr)
+                    for _ in range(3):
+                        sg.replay()
+                    torch.cuda.synchronize()
+                    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                    e0.record()
+                    for _ in range(iters):
+                        sg.replay()
+                    e1.record()
+                    torch.cuda.synchronize()
+                    row["graph_" + name + "_us"] = round(e0.elapsed_time(e1) / iters * 1e3, 1)
+                    del sg
                 print(json.dumps(row), flush=True)
 
 

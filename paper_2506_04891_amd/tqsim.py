@@ -302,6 +302,50 @@ class Circuit:
         return gw[: self.n_weights], gx[:, : self.n_features]
 
 
+class StepGraph:
+    """One step of a circuit on fixed device tensors -- forward, <Z_i> and, when
+    ``grad_expz`` is given, the adjoint gradient -- captured once as a HIP
+    graph.  ``replay()`` reruns the step: it reads the current contents of
+    ``weights``, ``features`` and ``grad_expz`` (update them in place between
+    replays) and refreshes ``expz``, ``grad_weights`` and ``grad_features``.
+    Small calls (few qubits, batch 1) are bound by the host's per-launch cost,
+    which a replay does not pay.  The graph holds its own state and
+    workspace; the circuit must outlive it."""
+
+    def __init__(self, circ, weights, features, grad_expz=None):
+        batch = features.shape[0]
+        dev = features.device
+        self.circ = circ.prepare()
+        self.weights, self.features, self.grad_expz = weights, features, grad_expz
+        self.state = torch.empty((batch, 2 ** circ.n), dtype=circ.complex_dtype, device=dev)
+        self.ws = circ.new_workspace(batch, True, dev)
+        self.grad_weights = self.grad_features = None
+        release_pending()
+        side = torch.cuda.Stream()
+        side.wait_stream(torch.cuda.current_stream())
+        with torch.cuda.stream(side):
+            self._step()
+        torch.cuda.current_stream().wait_stream(side)
+        torch.cuda.synchronize()
+        self.graph = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(self.graph):
+            self._step()
+
+    def _step(self):
+        c = self.circ
+        c.forward(self.weights, self.features, state=self.state, ws=self.ws)
+        self.expz = c.expval_z(self.state, ws=self.ws)
+        if self.grad_expz is not None:
+            self.grad_weights, self.grad_features = c.adjoint_grad(self.weights, self.features, self.state,
+                                                                   self.grad_expz, ws=self.ws)
+
+    def replay(self):
+        """Run the captured step on the current stream; returns (expz,
+        grad_weights, grad_features), the graph's own output tensors."""
+        self.graph.replay()
+        return self.expz, self.grad_weights, self.grad_features
+
+
 class QCircuitFn(torch.autograd.Function):
     """<Z_i> of a circuit, differentiable in weights and features by the adjoint
     method.  Only the final state is kept for backward (no intermediate

@@ -372,6 +372,45 @@ def test_step_graph_replays_equal_eager(name):
     assert np.max(np.abs(gx - o["gx"])) / np.max(np.abs(o["gx"])) <= 1e-4
 
 
+@pytest.mark.parametrize("n,B,with_grad", [(4, 1, True), (6, 3, False), (14, 1, True), (16, 5, True)])
+def test_step_graph_helper(n, B, with_grad):
+    """tqsim.StepGraph: replays alternate with eager steps and program work;
+    each replay equals the eager step bit for bit, also after the weights and
+    features are changed in place between replays; one replay is checked
+    against the oracle."""
+    layers = W.circuit_rz_ry_cnot(n, 3, "qdi")
+    w, x = W.draw_params(n, layers, B, "normal", 7)
+    g = W.upstream(B, n, "normal", 7)
+    note(f"case step graph n={n} B={B} grad={with_grad}")
+    dev = torch.device("cuda")
+    c = _circuit(n, layers, "c64")
+    wt, xt, gt = (torch.tensor(v, device=dev) for v in (w, x, g))
+    sg = T.StepGraph(c, wt, xt, gt if with_grad else None)
+    st = torch.empty((B, 2 ** n), dtype=c.complex_dtype, device=dev)
+    ws = c.new_workspace(B, True, dev)
+    for r in range(4):
+        if r == 2:
+            wt.mul_(0.5).add_(0.25)
+            xt.mul_(-1.0)
+        out = sg.replay()
+        torch.cuda.synchronize()
+        got = [None if t is None else t.clone() for t in out]
+        _ = torch.randn(1000, device=dev).sum().item()   # program work between replays
+        c.forward(wt, xt, state=st, ws=ws)
+        ref = [c.expval_z(st, ws=ws)]
+        ref += list(c.adjoint_grad(wt, xt, st, gt, ws=ws)) if with_grad else [None, None]
+        torch.cuda.synchronize()
+        for a, b in zip(got, ref):
+            assert (a is None) == (b is None)
+            if a is not None:
+                assert torch.equal(a, b), (n, B, r)
+    o = oracle_run(n, layers, wt.cpu().numpy(), xt.cpu().numpy(), g)
+    np.testing.assert_allclose(got[0].cpu().numpy(), o["e"], atol=2e-5)
+    if with_grad:
+        gw = got[1].cpu().numpy()
+        assert np.max(np.abs(gw - o["gw"])) <= 1e-4 * max(np.max(np.abs(o["gw"])), 1e-30)
+
+
 # ------------------------------------------- stored-state backpropagation --
 
 @pytest.mark.parametrize("name,builder,dist", [
