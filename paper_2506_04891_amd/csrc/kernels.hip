@@ -1235,6 +1235,13 @@ __device__ __forceinline__ void wht16(T (&w)[NREG]) {
     }
 }
 
+// The 16 register values as one vector: an element chosen by a wave-uniform
+// index is then one indexed register move (no branch per pick).
+template <typename T>
+struct Vec16 {
+  typedef T type __attribute__((ext_vector_type(16)));
+};
+
 template <typename T>
 __device__ __forceinline__ T wht_pick(const T (&w)[NREG], int m) {
   switch (m) {
@@ -1740,22 +1747,25 @@ __device__ __forceinline__ void run_stage(const Ctx<T, K> &c, const PassArgs<T> 
         if (__builtin_amdgcn_readfirstlane(c.seg_log) == 6) {
           // whole-wave segments: the terms' sums reduced eight at a time as one
           // transposed tree; lane k of the wave writes term k of the chunk
+          typename Vec16<T>::type wv;
+#pragma unroll
+          for (int j = 0; j < NREG; ++j) wv[j] = w[j];
           for (int k0 = 0; k0 < op.r1; k0 += 8) {
             double v8[8];
             int myacc = -1;
+            // all eight descriptors requested at once (the planner pads the
+            // table past the last op's terms); entries past r1 count zero
 #pragma unroll
             for (int q = 0; q < 8; ++q) {
-              v8[q] = 0.0;
-              if (k0 + q < op.r1) {
-                kptr<DevTermGrad> tg = a.tgrads + op.mat + k0 + q;
-                const int tacc = uni(tg->acc), m = uni(tg->m);
-                const uint32_t tmask = uniu(tg->tmask), gmask = uniu(tg->gmask);
-                const int neg =
-                    (__builtin_popcount(c.base & gmask) + __builtin_popcount((uint32_t)tt & tmask)) & 1;
-                const double val = (double)wht_pick(w, m);
-                v8[q] = neg ? -val : val;
-                if ((c.lane & 7) == q) myacc = tacc;
-              }
+              kptr<DevTermGrad> tg = a.tgrads + op.mat + k0 + q;
+              const int tacc = uni(tg->acc), m = uni(tg->m) & (NREG - 1);
+              const uint32_t tmask = uniu(tg->tmask), gmask = uniu(tg->gmask);
+              const bool ok = k0 + q < op.r1;
+              const int neg =
+                  (__builtin_popcount(c.base & gmask) + __builtin_popcount((uint32_t)tt & tmask)) & 1;
+              const double val = (double)wv[m];
+              v8[q] = ok ? (neg ? -val : val) : 0.0;
+              if (ok && (c.lane & 7) == q) myacc = tacc;
             }
             const double tot = wave_sum8_transposed(v8, c.lane);
             if (c.sub == 0 && c.lane < 8 && myacc >= 0) c.pslot[(long long)myacc * c.pstride] = tot;

@@ -1580,6 +1580,14 @@ static std::string emit(Plan &P) {
     P.dpass.push_back(d);
   }
   P.units_total = E.acc_prefix;
+  // eight inert entries after the diagonal-term gradients: a pass reads term
+  // descriptors eight at a time without bounds tests
+  for (int q = 0; q < 8; ++q) {
+    DevTermGrad g;
+    std::memset(&g, 0, sizeof g);
+    g.acc = -1;
+    P.dtgrad.push_back(g);
+  }
   for (DevStage &st : P.dstage) {
     for (int k = 0; k < RB; ++k) st.rsorted[k] = st.rbits[k];
     std::sort(st.rsorted, st.rsorted + RB);
