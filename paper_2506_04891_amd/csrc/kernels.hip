@@ -1242,17 +1242,6 @@ struct Vec16 {
   typedef T type __attribute__((ext_vector_type(16)));
 };
 
-template <typename T>
-__device__ __forceinline__ T wht_pick(const T (&w)[NREG], int m) {
-  switch (m) {
-#define C(i) \
-  case i: TQS_CASE_MARK(w##i); return w[i];
-    C(0) C(1) C(2) C(3) C(4) C(5) C(6) C(7) C(8) C(9) C(10) C(11) C(12) C(13) C(14)
-#undef C
-    default: TQS_CASE_MARK(w15); return w[15];
-  }
-}
-
 // Phase angle of entry `idx` of a diagonal op's split tables (the TL entries
 // first, then TH) for the tile whose bits outside the tile are `base`, and
 // sample `smp` for terms with per-sample angles: the sum of the term angles
@@ -1771,12 +1760,15 @@ __device__ __forceinline__ void run_stage(const Ctx<T, K> &c, const PassArgs<T> 
             if (c.sub == 0 && c.lane < 8 && myacc >= 0) c.pslot[(long long)myacc * c.pstride] = tot;
           }
         } else {
+          typename Vec16<T>::type wv;
+#pragma unroll
+          for (int j = 0; j < NREG; ++j) wv[j] = w[j];
           for (int k = 0; k < op.r1; ++k) {
             kptr<DevTermGrad> tg = a.tgrads + op.mat + k;
-            const int tacc = uni(tg->acc), m = uni(tg->m);
+            const int tacc = uni(tg->acc), m = uni(tg->m) & (NREG - 1);
             const uint32_t tmask = uniu(tg->tmask), gmask = uniu(tg->gmask);
             const int neg = (__builtin_popcount(c.base & gmask) + __builtin_popcount((uint32_t)tt & tmask)) & 1;
-            T val = wht_pick(w, m);
+            T val = wv[m];
             if (neg) val = -val;
             write_acc(c, a, val, tacc);
           }
