@@ -372,18 +372,21 @@ def test_step_graph_replays_equal_eager(name):
     assert np.max(np.abs(gx - o["gx"])) / np.max(np.abs(o["gx"])) <= 1e-4
 
 
-@pytest.mark.parametrize("n,B,with_grad", [(4, 1, True), (6, 3, False), (14, 1, True), (16, 5, True)])
-def test_step_graph_helper(n, B, with_grad):
+@pytest.mark.parametrize("n,B,with_grad,backward", [(4, 1, True, "adjoint"), (6, 3, False, "adjoint"),
+                                                    (14, 1, True, "adjoint"), (16, 5, True, "adjoint"),
+                                                    (16, 5, True, "stored")])
+def test_step_graph_helper(n, B, with_grad, backward):
     """tqsim.StepGraph: replays alternate with eager steps and program work;
     each replay equals the eager step bit for bit, also after the weights and
     features are changed in place between replays; one replay is checked
-    against the oracle."""
+    against the oracle.  The stored-state backward reads the pass outputs the
+    captured forward kept in the graph's own workspace."""
     layers = W.circuit_rz_ry_cnot(n, 3, "qdi")
     w, x = W.draw_params(n, layers, B, "normal", 7)
     g = W.upstream(B, n, "normal", 7)
-    note(f"case step graph n={n} B={B} grad={with_grad}")
+    note(f"case step graph n={n} B={B} grad={with_grad} backward={backward}")
     dev = torch.device("cuda")
-    c = _circuit(n, layers, "c64")
+    c = T.Circuit(n, layers, "c64", backward=backward)
     wt, xt, gt = (torch.tensor(v, device=dev) for v in (w, x, g))
     sg = T.StepGraph(c, wt, xt, gt if with_grad else None)
     st = torch.empty((B, 2 ** n), dtype=c.complex_dtype, device=dev)
