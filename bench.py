@@ -45,6 +45,10 @@ def parse():
                    help="skip the complex128 headline, the 4-qubit and the 12-qubit legs")
     p.add_argument("--serve-warmup", type=int, default=50,
                    help="warm-up requests per arrival rate, left out of the statistics (200 for the full protocol)")
+    p.add_argument("--serve-light-during-heavy", type=int, default=1,
+                   help="continuous path: at most this many small launches beside a heavy one (negative: no cap)")
+    p.add_argument("--serve-compare-light-cap", type=int, default=None,
+                   help="also run the continuous path under this cap at every point")
     p.add_argument("--serve-only", action="store_true",
                    help="run only the serving comparison and print its JSON")
     p.add_argument("--no-graph", action="store_true", help="time eager launches instead of a replayed HIP graph")
@@ -179,12 +183,15 @@ def step_stats(per):
             "max_ms": round(float(a.max()), 4)}
 
 
-def serving_bench(n_req, n_max, fracs, seed=0, streams=4, budget=160 << 30, heavy=256 << 20, warm=200):
+def serving_bench(n_req, n_max, fracs, seed=0, streams=4, budget=160 << 30, heavy=256 << 20, warm=200,
+                  light_during_heavy=1, compare_light=None):
     """Continuous batching vs the plain per-request path on one Poisson trace of
     rotation + CNOT-ring circuits (qubits U{6..n_max}, batch log-U[1, 512],
     blocks U{2..20}, 30% forward+gradient): `warm` requests, then `n_req`
     measured ones, per arrival rate.  Launches reserving more than `heavy`
-    bytes fill the device alone and run one at a time."""
+    bytes run one at a time, with at most `light_during_heavy` small launches
+    beside them (None: every free stream).  With `compare_light`, each point
+    also runs the continuous path under that cap instead."""
     import numpy as np
     import workloads as W
     from paper_2506_04891_amd.serve import GpuExecutor, Request, Server
@@ -197,9 +204,10 @@ def serving_bench(n_req, n_max, fracs, seed=0, streams=4, budget=160 << 30, heav
             reqs.append((t.t_arrive, Request(t.n, layers, w, x, want_grad=t.want_grad, rid=t.rid)))
         return reqs
 
-    def run(reqs, plain, ex):
+    def run(reqs, plain, ex, light=light_during_heavy):
         print(f"serving: {len(reqs)} requests, {'plain' if plain else 'continuous'}", file=sys.stderr, flush=True)
-        srv = Server(ex, budget_bytes=budget, streams=streams, plain=plain, heavy_bytes=heavy)
+        srv = Server(ex, budget_bytes=budget, streams=streams, plain=plain, heavy_bytes=heavy,
+                     light_during_heavy=light)
         t0 = time.perf_counter()
         futs = []
         for ta, r in reqs:
@@ -223,18 +231,29 @@ def serving_bench(n_req, n_max, fracs, seed=0, streams=4, budget=160 << 30, heav
     req_per_s = sat["requests"] / max(1e-9, (sat["evals"] / max(sat["evals_per_s"], 1e-9)))
     out = {"trace": f"{warm} warm-up + {n_req} measured requests per point, qubits U{{6..{n_max}}}, batch log-U[1,512], blocks U{{2..20}}, "
                     f"30% forward+gradient, seed {seed}; {streams} streams, one launch above "
-                    f"{heavy >> 20} MiB at a time; warm circuits and graphs",
+                    f"{heavy >> 20} MiB at a time"
+                    + (f" with at most {light_during_heavy} other launch(es) beside it" if light_during_heavy is not None else "")
+                    + "; warm circuits and graphs",
            "saturation": {"requests_per_s": round(req_per_s, 1), "evals_per_s": round(sat["evals_per_s"], 1)},
            "points": []}
     for frac in fracs:
         qps = frac * req_per_s
         cb = run(make(qps), False, ex)
         pl = run(make(qps), True, ex_plain)
-        out["points"].append({"qps": round(qps, 1), "frac_of_saturation": frac,
-                              "continuous": {k: round(cb[k], 3) for k in ("p50_ms", "p99_ms", "evals_per_s")}
-                              | {"launches": cb["launches"]},
-                              "plain": {k: round(pl[k], 3) for k in ("p50_ms", "p99_ms", "evals_per_s")}})
+        point = {"qps": round(qps, 1), "frac_of_saturation": frac,
+                 "continuous": {k: round(cb[k], 3) for k in ("p50_ms", "p99_ms", "evals_per_s")}
+                 | {"launches": cb["launches"]},
+                 "plain": {k: round(pl[k], 3) for k in ("p50_ms", "p99_ms", "evals_per_s")}}
+        if compare_light is not None:
+            cc = run(make(qps), False, ex, light=compare_light)
+            point[f"continuous_light_cap_{compare_light}"] = (
+                {k: round(cc[k], 3) for k in ("p50_ms", "p99_ms", "evals_per_s")} | {"launches": cc["launches"]})
+        out["points"].append(point)
     return out
+
+
+def light_cap(v):
+    return None if v is None or v < 0 else v
 
 
 def time_graph(jobs, steps, warmup):
@@ -809,7 +828,9 @@ def main():
         return
     if a.serve_only:
         print(json.dumps(serving_bench(a.serve_requests, a.serve_max_qubits,
-                                       [float(f) for f in a.serve_qps_fracs.split(",")], warm=a.serve_warmup)))
+                                       [float(f) for f in a.serve_qps_fracs.split(",")], warm=a.serve_warmup,
+                                       light_during_heavy=light_cap(a.serve_light_during_heavy),
+                                       compare_light=a.serve_compare_light_cap)))
         return
 
     def errs(j):
@@ -911,7 +932,7 @@ def main():
     if not a.no_serve:
         out["serving"] = serving_bench(a.serve_requests, a.serve_max_qubits,
                                        [float(f) for f in a.serve_qps_fracs.split(",")],
-                                       warm=a.serve_warmup)
+                                       warm=a.serve_warmup, light_during_heavy=light_cap(a.serve_light_during_heavy))
     out["cpu_baseline"] = cpu
     if cpu_pool is not None:
         out["cpu_baseline_all_cores"] = cpu_pool.pop("all_cores")

@@ -17,7 +17,9 @@ forward + gradient) arrive at any time.  A scheduler thread
 * keeps at most one *heavy* launch (reservation above ``heavy_bytes``) in
   flight: a large circuit saturates the device by itself, so two of them
   sharing it only stretch both, while small requests still overlap with it
-  and are admitted past a heavy request that has to wait;
+  and are admitted past a heavy request that has to wait; with
+  ``light_during_heavy`` only that many small launches run beside it, so the
+  heavy launch, which sets the tail latency, keeps most of the device;
 * records arrival -> result latency per request.
 
 ``Server(..., plain=True)`` is the plain per-request path used as the
@@ -109,12 +111,17 @@ class Server:
     streams: launches in flight at once.  max_rows: rows per coalesced launch.
     heavy_bytes: launches reserving more are heavy; one heavy launch at a time
     (None: no limit).
+    light_during_heavy: while a heavy launch runs, at most this many other
+    launches beside it (None: every free stream), so that the heavy one keeps
+    most of the device.
     plain: the per-request baseline (one stream, FIFO, no coalescing)."""
 
     def __init__(self, executor, budget_bytes, streams=4, max_rows=1024, plain=False, poll_s=50e-6,
-                 paused=False, heavy_bytes=None):
+                 paused=False, heavy_bytes=None, light_during_heavy=None):
         self.ex = executor
         self.heavy_bytes = None if heavy_bytes is None else int(heavy_bytes)
+        self.light_during_heavy = None if light_during_heavy is None else int(light_during_heavy)
+        self.max_light_beside_heavy = 0
         self._heavy_inflight = 0
         self.max_heavy_inflight = 0
         self._paused = paused
@@ -266,8 +273,12 @@ class Server:
                     if g.reserve > avail:
                         self._requeue_front(g)     # wait for memory to free up
                         break
-                    g.slot = self._free_slots.pop()
                     g.heavy = self.heavy_bytes is not None and not self.plain and g.reserve > self.heavy_bytes
+                    if (not g.heavy and self._heavy_inflight and self.light_during_heavy is not None
+                            and sum(1 for x in self._inflight if not x.heavy) >= self.light_during_heavy):
+                        self._requeue_front(g)     # the heavy launch keeps the device
+                        break
+                    g.slot = self._free_slots.pop()
                     self._heavy_inflight += g.heavy
                     self.max_heavy_inflight = max(self.max_heavy_inflight, self._heavy_inflight)
                     self._reserved += g.reserve
@@ -276,6 +287,9 @@ class Server:
                         g.handle = self.ex.launch(g, g.slot)
                         self.launches += 1
                         self._inflight.append(g)
+                        if self._heavy_inflight:
+                            self.max_light_beside_heavy = max(self.max_light_beside_heavy,
+                                                              sum(1 for x in self._inflight if not x.heavy))
                     except Exception as e:
                         self._fail(g, e)
                 if not self._inflight and not any(self._pending.values()):

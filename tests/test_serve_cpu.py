@@ -110,6 +110,24 @@ def test_plain_path_is_one_request_per_launch():
     assert all(len(l) == 1 for l in ex.launched) and len(ex.launched) == len(reqs)
 
 
+def test_light_launches_beside_a_heavy_one_are_capped():
+    """With light_during_heavy = 1, at most one small launch runs beside a heavy
+    one, small ones still overlap with it, and every result equals the request
+    alone."""
+    reqs = _requests(40, seed=7, b_max=32)
+    row = 1 << 20
+    ex = HostExecutor(oracle_fn, delay=0.004, row_bytes=row)
+    srv = Server(ex, budget_bytes=1 << 40, streams=4, heavy_bytes=8 * row, light_during_heavy=1, paused=True)
+    futs = [srv.submit(r) for r in reqs]
+    srv.resume()
+    res = [f.result(timeout=60) for f in futs]
+    srv.close()
+    assert srv.max_heavy_inflight == 1
+    assert srv.max_light_beside_heavy == 1
+    for r, got in zip(reqs, res):
+        np.testing.assert_array_equal(got.expz, oracle_fn(r).expz)
+
+
 def test_bucket():
     assert [bucket(b) for b in (1, 2, 3, 5, 8, 9, 512, 513)] == [1, 2, 4, 8, 8, 16, 512, 1024]
 
